@@ -1,0 +1,124 @@
+/*
+ * polymul.h -- exact multiplication in Z_q[x]/(x^n + 1) on gfx950 int8 MFMA.
+ *
+ * The operation (paper Sec. 2.1, Eq. (1) coefficient form; Sec. 2.2 fold rule
+ * and Eq. (3)):  given a(x), b(x) with coefficients a_i, b_i in Z_q, return
+ *
+ *     c_j = ( sum_{i<=j} a_i b_{j-i} - sum_{i>j} a_i b_{n+j-i} ) mod q,   0 <= j < n,
+ *
+ * as the least non-negative residue.  The library computes it as a dense
+ * integer matrix product (Sec. 2.2: one operand becomes the negacyclic
+ * Toeplitz matrix of Eq. (3)), split into balanced signed 8-bit limbs
+ * (Sec. 2.4, strategy (ii): several small units per coefficient) and tiled
+ * over the degree (Sec. 2.5, divide and conquer).
+ *
+ * Conventions shared by every entry point:
+ *   - Polynomials are stored lowest degree first, one machine word per
+ *     coefficient (uint32_t for q < 2^32, uint64_t for q < 2^64), products
+ *     laid out back to back: element [p][j] is at offset p*n + j.
+ *   - a, b, c are DEVICE pointers owned by the caller.  The library never
+ *     frees or retains them (plans keep the pointers they were given).
+ *   - Input words are read mod q (any 32/64-bit value is accepted); outputs
+ *     are canonical, in [0, q).
+ *   - n must be a power of two, 1 <= n <= 65536; q >= 2 (prime or not).
+ *   - c must not overlap a or b (every output reads all of a and b).
+ *   - Every call is asynchronous on `stream` (0 = the null stream).  Argument
+ *     errors are returned before any HIP call is made; launch errors are
+ *     reported as POLYMUL_EDEVICE.  No exception crosses this interface.
+ *   - batch == 0 (or count == 0) is a successful no-op.
+ *   - Stateless calls are thread-safe.
+ */
+#ifndef POLYMUL_H
+#define POLYMUL_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    POLYMUL_OK = 0,
+    POLYMUL_EINVAL = 1,        /* bad n, q, L, count, null pointer or size overflow */
+    POLYMUL_EALIAS = 2,        /* c overlaps a or b */
+    POLYMUL_EUNSUPPORTED = 3,  /* valid arguments outside what this build implements */
+    POLYMUL_ENOMEM = 4,        /* device or host allocation failed (plans only) */
+    POLYMUL_EDEVICE = 5        /* a HIP call or kernel launch failed */
+} polymul_status;
+
+/* Human-readable name of a status code (static storage, never NULL). */
+const char* polymul_status_string(polymul_status s);
+
+/*
+ * c[p] = a[p] * b[p] in Z_q[x]/(x^n+1) for p < batch, q < 2^32.
+ * Paper Sec. 2.2 (Eq. (3)) for one pair; a batch of independent pairs is the
+ * independent-instance parallelism of Sec. 2.4.
+ * a, b, c: device, uint32_t[batch][n].
+ */
+polymul_status polymul_negacyclic(const uint32_t* a, const uint32_t* b, uint32_t* c,
+                                  uint64_t n, uint32_t q, uint64_t batch, hipStream_t stream);
+
+/*
+ * Same for a 64-bit modulus, q < 2^64 (for example 2^64 - 2^32 + 1).
+ * a, b, c: device, uint64_t[batch][n].
+ */
+polymul_status polymul_negacyclic_u64(const uint64_t* a, const uint64_t* b, uint64_t* c,
+                                      uint64_t n, uint64_t q, uint64_t batch, hipStream_t stream);
+
+/*
+ * RNS form (paper Sec. 2.4): each coefficient is held as its residues modulo
+ * L moduli q[0..L-1]; the product is computed independently per residue
+ * channel and the result stays in RNS (no CRT reconstruction).
+ * a, b, c: device, uint32_t[batch][L][n]; channel l is reduced mod q[l].
+ * q: HOST array of L moduli (each >= 2, < 2^32), copied during the call.
+ */
+polymul_status polymul_negacyclic_rns(const uint32_t* a, const uint32_t* b, uint32_t* c,
+                                      uint64_t n, const uint32_t* q, uint32_t L,
+                                      uint64_t batch, hipStream_t stream);
+
+/*
+ * The same product as polymul_negacyclic computed with plain 32x32->64-bit
+ * integer multiply-adds (schoolbook, no matrix units).  A comparison baseline
+ * for the MFMA path; never used as a fallback.
+ */
+polymul_status polymul_negacyclic_plain(const uint32_t* a, const uint32_t* b, uint32_t* c,
+                                        uint64_t n, uint32_t q, uint64_t batch, hipStream_t stream);
+
+/*
+ * Grouped products of uneven size in one persistent launch, replayed from a
+ * HIP graph (paper Sec. 2.6-2.7: parameters fixed once per configuration,
+ * Algorithm 1's GenConfig/ExtractDimensions done at plan time).
+ *
+ * Group g holds `count` independent products of degree bound n over Z_q:
+ *   a, b, c: device, count*n words of elem_bytes (4: q < 2^32; 8: q < 2^64).
+ * polymul_plan_create copies the group table, builds and uploads the work
+ * list and captures the graph; the plan owns only that device work list, its
+ * queue counter and the graph.  Pointers are baked in: later executes read
+ * and write the same buffers.  A plan must not be executed concurrently with
+ * itself.  flags: 0, or POLYMUL_PLAN_NO_GRAPH to launch directly each time.
+ */
+typedef struct {
+    const void* a;
+    const void* b;
+    void* c;
+    uint64_t n;
+    uint64_t q;
+    uint64_t count;
+    uint32_t elem_bytes;
+} polymul_group;
+
+typedef struct polymul_plan polymul_plan;
+
+#define POLYMUL_PLAN_NO_GRAPH 1u
+
+polymul_status polymul_plan_create(polymul_plan** plan, const polymul_group* groups,
+                                   uint32_t ngroups, uint32_t flags);
+polymul_status polymul_plan_execute(polymul_plan* plan, hipStream_t stream);
+polymul_status polymul_plan_destroy(polymul_plan* plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* POLYMUL_H */

@@ -1,0 +1,20 @@
+"""MI355X split-limb int8-MFMA negacyclic polynomial multiplication.
+
+The compute path lives in ``libpolymul.so`` (HIP for gfx950, C ABI declared in
+``include/polymul.h``); ``binding`` wraps it with ctypes for torch device
+tensors.  Nothing here computes a product on the CPU.
+"""
+from .binding import (  # noqa: F401
+    PolymulError,
+    lib_path,
+    load_library,
+    polymul_negacyclic,
+    polymul_negacyclic_plain,
+    polymul_negacyclic_rns,
+    polymul_negacyclic_u64,
+    polymul_plan_create,
+    polymul_plan_destroy,
+    polymul_plan_execute,
+    polymul_status_string,
+    Plan,
+)

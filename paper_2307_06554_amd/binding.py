@@ -1,0 +1,196 @@
+"""ctypes binding of libpolymul.so: argument marshalling only.
+
+Each function has the name of the C entry point it calls.  Tensors are torch
+device tensors used as plain device memory (int32/uint32 for 32-bit words,
+int64/uint64 for 64-bit words, reinterpreted bit for bit); the call is queued
+on torch's current stream.  Every step of the product runs in the library's
+HIP kernels; there is no CPU fallback: a missing library raises.
+"""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_NAME = "libpolymul.so"
+_lib = None
+
+STATUS = {0: "POLYMUL_OK", 1: "POLYMUL_EINVAL", 2: "POLYMUL_EALIAS", 3: "POLYMUL_EUNSUPPORTED",
+          4: "POLYMUL_ENOMEM", 5: "POLYMUL_EDEVICE"}
+POLYMUL_PLAN_NO_GRAPH = 1
+
+# name -> (restype, argtypes) exactly as declared in include/polymul.h
+_vp, _u32, _u64 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64
+_SIGNATURES = {
+    "polymul_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "polymul_negacyclic": (ctypes.c_int, [_vp, _vp, _vp, _u64, _u32, _u64, _vp]),
+    "polymul_negacyclic_u64": (ctypes.c_int, [_vp, _vp, _vp, _u64, _u64, _u64, _vp]),
+    "polymul_negacyclic_rns": (ctypes.c_int, [_vp, _vp, _vp, _u64, _vp, _u32, _u64, _vp]),
+    "polymul_negacyclic_plain": (ctypes.c_int, [_vp, _vp, _vp, _u64, _u32, _u64, _vp]),
+    "polymul_plan_create": (ctypes.c_int, [ctypes.POINTER(_vp), _vp, _u32, _u32]),
+    "polymul_plan_execute": (ctypes.c_int, [_vp, _vp]),
+    "polymul_plan_destroy": (ctypes.c_int, [_vp]),
+}
+
+
+class PolymulError(RuntimeError):
+    def __init__(self, status, where=""):
+        self.status = status
+        super().__init__(f"{where}: {STATUS.get(status, status)}")
+
+
+class _Group(ctypes.Structure):
+    _fields_ = [("a", _vp), ("b", _vp), ("c", _vp), ("n", _u64), ("q", _u64), ("count", _u64),
+                ("elem_bytes", _u32)]
+
+
+def lib_path():
+    return os.path.join(_HERE, _LIB_NAME)
+
+
+def load_library():
+    """Load libpolymul.so (built in-tree by __graft_entry__.build()); raise if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = lib_path()
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build the HIP library first (__graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def polymul_status_string(status):
+    return load_library().polymul_status_string(int(status)).decode()
+
+
+def _check(status, where):
+    if status != 0:
+        raise PolymulError(status, where)
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _words(t, nbytes, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.element_size() != nbytes or t.is_floating_point() or t.is_complex():
+        raise TypeError(f"{name} must hold {8 * nbytes}-bit integer words")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def polymul_negacyclic(a, b, q, out=None, stream=None):
+    """c = a*b in Z_q[x]/(x^n+1) for 32-bit words [..., n], q < 2^32 (int8-MFMA path)."""
+    import torch
+    if a.shape != b.shape or a.dim() < 1:
+        raise ValueError("a and b must have the same shape [..., n]")
+    n = a.shape[-1]
+    batch = a.numel() // n if n else 0
+    c = torch.empty_like(a) if out is None else out
+    if c.shape != a.shape:
+        raise ValueError("out has the wrong shape")
+    st = load_library().polymul_negacyclic(_words(a, 4, "a"), _words(b, 4, "b"), _words(c, 4, "out"),
+                                          n, int(q), batch, _stream(stream))
+    _check(st, "polymul_negacyclic")
+    return c
+
+
+def polymul_negacyclic_plain(a, b, q, out=None, stream=None):
+    """Same product with the plain integer schoolbook kernel (baseline)."""
+    import torch
+    if a.shape != b.shape or a.dim() < 1:
+        raise ValueError("a and b must have the same shape [..., n]")
+    n = a.shape[-1]
+    batch = a.numel() // n if n else 0
+    c = torch.empty_like(a) if out is None else out
+    st = load_library().polymul_negacyclic_plain(_words(a, 4, "a"), _words(b, 4, "b"), _words(c, 4, "out"),
+                                                n, int(q), batch, _stream(stream))
+    _check(st, "polymul_negacyclic_plain")
+    return c
+
+
+def polymul_negacyclic_u64(a, b, q, out=None, stream=None):
+    """c = a*b in Z_q[x]/(x^n+1) for 64-bit words [..., n], q < 2^64."""
+    import torch
+    if a.shape != b.shape or a.dim() < 1:
+        raise ValueError("a and b must have the same shape [..., n]")
+    n = a.shape[-1]
+    batch = a.numel() // n if n else 0
+    c = torch.empty_like(a) if out is None else out
+    st = load_library().polymul_negacyclic_u64(_words(a, 8, "a"), _words(b, 8, "b"), _words(c, 8, "out"),
+                                              n, int(q), batch, _stream(stream))
+    _check(st, "polymul_negacyclic_u64")
+    return c
+
+
+def polymul_negacyclic_rns(a, b, qs, out=None, stream=None):
+    """RNS form: a, b are 32-bit words [batch, L, n]; channel l is taken mod qs[l]."""
+    import torch
+    if a.shape != b.shape or a.dim() != 3:
+        raise ValueError("a and b must be [batch, L, n]")
+    batch, L, n = a.shape
+    if len(qs) != L:
+        raise ValueError("need one modulus per channel")
+    c = torch.empty_like(a) if out is None else out
+    qarr = (ctypes.c_uint32 * L)(*[int(x) for x in qs])
+    st = load_library().polymul_negacyclic_rns(_words(a, 4, "a"), _words(b, 4, "b"), _words(c, 4, "out"),
+                                              n, ctypes.cast(qarr, ctypes.c_void_p), L, batch, _stream(stream))
+    _check(st, "polymul_negacyclic_rns")
+    return c
+
+
+def polymul_plan_create(groups, flags=0):
+    """groups: list of (a, b, c, n, q) device tensors [count, n] (32- or 64-bit words).
+    Returns an opaque plan handle (ctypes c_void_p)."""
+    arr = (_Group * max(1, len(groups)))()
+    for i, (a, b, c, n, q) in enumerate(groups):
+        eb = a.element_size()
+        count = a.numel() // n if n else 0
+        arr[i] = _Group(_words(a, eb, "a").value, _words(b, eb, "b").value, _words(c, eb, "c").value,
+                        int(n), int(q), int(count), eb)
+    handle = ctypes.c_void_p()
+    st = load_library().polymul_plan_create(ctypes.byref(handle), ctypes.cast(arr, ctypes.c_void_p),
+                                           len(groups), int(flags))
+    _check(st, "polymul_plan_create")
+    return handle
+
+
+def polymul_plan_execute(plan, stream=None):
+    _check(load_library().polymul_plan_execute(plan, _stream(stream)), "polymul_plan_execute")
+
+
+def polymul_plan_destroy(plan):
+    _check(load_library().polymul_plan_destroy(plan), "polymul_plan_destroy")
+
+
+class Plan:
+    """Owning wrapper: keeps the tensors alive as long as the plan."""
+
+    def __init__(self, groups, flags=0):
+        self._groups = list(groups)
+        self.handle = polymul_plan_create(self._groups, flags)
+
+    def execute(self, stream=None):
+        polymul_plan_execute(self.handle, stream)
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            polymul_plan_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

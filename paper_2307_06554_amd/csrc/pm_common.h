@@ -1,0 +1,95 @@
+// Internal definitions of the GPU library (host and device).  Not installed.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pm {
+
+// ---------------------------------------------------------------------------
+// Balanced signed radix-2^8 limbs (paper Sec. 2.4, strategy (ii): a wide
+// coefficient is held as several small units that the matrix engine takes
+// natively).  With L limbs the digit window is
+//     W_L = [-128 * S_L, 127 * S_L],  S_L = sum_{i<L} 256^i,
+// which holds exactly 256^L consecutive integers, so every residue class mod
+// q <= 256^L has a representative in it: x itself when x <= 127*S_L, else
+// x - q.  Adding BIAS_L = 128*S_L maps the window onto [0, 256^L) and the
+// bytes of (v + BIAS_L) XOR 0x80.. are the digits d_i in [-128, 127] with
+// v = sum_i d_i 256^i.  No digit is ever negated (the negative wrap sign of
+// Eq. (3) is carried by the digits of q - x instead), so -128 never overflows.
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr uint64_t limb_sum(int L) {
+  uint64_t s = 0;
+  for (int i = 0; i < L; ++i) s |= (uint64_t)1 << (8 * i);
+  return s;
+}
+__host__ __device__ constexpr uint64_t limb_bias(int L) { return 0x80ull * limb_sum(L); }
+__host__ __device__ constexpr uint64_t limb_top(int L) { return 0x7Full * limb_sum(L); }
+
+// Smallest limb count whose window covers q residues (q <= 256^L).
+inline int limbs_for_q32(uint32_t q) {
+  if (q <= 256u) return 1;
+  if (q <= 65536u) return 2;
+  if (q <= (1u << 24)) return 3;
+  return 4;
+}
+inline int limbs_for_q64(uint64_t q) {
+  int L = 1;
+  while (L < 8 && q > ((uint64_t)1 << (8 * L))) ++L;
+  return L;
+}
+
+// Per-modulus constants for the 32-bit-modulus paths.
+struct ModQ32 {
+  uint32_t q;
+  uint32_t thr;     // digit representative threshold: x <= thr ? x : x - q
+  uint64_t mu;      // floor(2^64 / q) for Barrett reduction (q >= 2)
+  uint64_t lift;    // multiple of q in [2^62, 2^62 + q): makes |x| < 2^62 non-negative
+  uint32_t r64;     // 2^64 mod q
+  uint32_t pad;
+};
+
+inline ModQ32 make_mod32(uint32_t q, int L) {
+  ModQ32 m{};
+  m.q = q;
+  uint64_t top = limb_top(L);
+  m.thr = top >= 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)top;
+  // floor(2^64 / q) = floor((2^64 - 1) / q) unless q divides 2^64 (q a power of two).
+  uint64_t mu = UINT64_MAX / q;
+  if ((q & (q - 1)) == 0) mu += 1;  // exact power of two: 2^64/q = (2^64-1)/q + 1
+  if (q == 1) mu = UINT64_MAX;       // unreachable (q >= 2 is validated)
+  m.mu = mu;
+  uint64_t k = ((uint64_t)1 << 62) / q + 1;
+  m.lift = k * q;
+  unsigned __int128 t = ((unsigned __int128)1 << 64) % q;
+  m.r64 = (uint32_t)t;
+  return m;
+}
+
+// Barrett: x mod q for any 64-bit x, q < 2^32.  With mu = floor(2^64/q) the
+// quotient estimate undershoots by at most 2, so r < 3q < 2^34.
+__device__ __forceinline__ uint32_t reduce_u64(uint64_t x, const ModQ32& m) {
+  uint64_t qe = __umul64hi(x, m.mu);
+  uint64_t r = x - qe * (uint64_t)m.q;
+  if (r >= m.q) r -= m.q;
+  if (r >= m.q) r -= m.q;
+  return (uint32_t)r;
+}
+// Signed |x| < 2^62.
+__device__ __forceinline__ uint32_t reduce_i64(int64_t x, const ModQ32& m) {
+  return reduce_u64((uint64_t)(x + (int64_t)m.lift), m);
+}
+
+// L digits of the residue x (already in [0, q)), packed little-endian in a word.
+template <int L>
+__device__ __forceinline__ uint32_t digits32(uint32_t x, uint32_t q, uint32_t thr) {
+  constexpr uint32_t B = (uint32_t)limb_bias(L);
+  uint32_t v = x <= thr ? x : x - q;  // wraps mod 2^32: the representative in W_L
+  return (v + B) ^ B;
+}
+// Digits of -x mod q.
+template <int L>
+__device__ __forceinline__ uint32_t neg_digits32(uint32_t x, uint32_t q, uint32_t thr) {
+  return digits32<L>(x == 0 ? 0u : q - x, q, thr);
+}
+
+}  // namespace pm

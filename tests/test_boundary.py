@@ -1,0 +1,113 @@
+"""The C ABI on the CPU: the library loads, exports what the header declares,
+and rejects bad arguments before touching the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2307_06554_amd as pm
+from paper_2307_06554_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "polymul.h")
+
+EINVAL, EALIAS, EUNSUPPORTED = 1, 2, 3
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(polymul_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    fns = header_functions()
+    for name in ("polymul_negacyclic", "polymul_negacyclic_u64", "polymul_negacyclic_rns",
+                 "polymul_negacyclic_plain", "polymul_plan_create", "polymul_plan_execute",
+                 "polymul_plan_destroy", "polymul_status_string"):
+        assert name in fns
+
+
+def test_library_exports_every_declared_symbol():
+    lib = pm.load_library()
+    for name in header_functions():
+        assert hasattr(lib, name), f"libpolymul.so does not export {name}"
+    assert set(header_functions()) <= set(binding._SIGNATURES), "binding misses an entry point"
+
+
+def test_status_strings():
+    for code, name in binding.STATUS.items():
+        assert pm.polymul_status_string(code).startswith(name)
+    assert "UNKNOWN" in pm.polymul_status_string(99)
+
+
+# Fake, never-dereferenced device addresses: argument errors must be reported first.
+A, B, C = 0x10000000, 0x20000000, 0x30000000
+
+
+def call(name, *args):
+    lib = pm.load_library()
+    return getattr(lib, name)(*args)
+
+
+@pytest.mark.parametrize("n", [0, 3, 6, 100, 131072, 1 << 40])
+def test_bad_degree(n):
+    assert call("polymul_negacyclic", A, B, C, n, 17, 1, None) == EINVAL
+    assert call("polymul_negacyclic_plain", A, B, C, n, 17, 1, None) == EINVAL
+    assert call("polymul_negacyclic_u64", A, B, C, n, 17, 1, None) == EINVAL
+
+
+@pytest.mark.parametrize("q", [0, 1])
+def test_bad_modulus(q):
+    assert call("polymul_negacyclic", A, B, C, 256, q, 1, None) == EINVAL
+    assert call("polymul_negacyclic_u64", A, B, C, 256, q, 1, None) == EINVAL
+    assert call("polymul_negacyclic_plain", A, B, C, 256, q, 1, None) == EINVAL
+
+
+def test_null_pointers():
+    for args in ((None, B, C), (A, None, C), (A, B, None)):
+        assert call("polymul_negacyclic", *args, 256, 17, 1, None) == EINVAL
+
+
+def test_zero_batch_is_a_noop():
+    assert call("polymul_negacyclic", None, None, None, 256, 17, 0, None) == 0
+    assert call("polymul_negacyclic_u64", None, None, None, 256, 17, 0, None) == 0
+    assert call("polymul_negacyclic_plain", None, None, None, 256, 17, 0, None) == 0
+
+
+def test_aliasing_is_rejected():
+    n, batch = 256, 4
+    nbytes = n * batch * 4
+    assert call("polymul_negacyclic", A, B, A, n, 17, batch, None) == EALIAS
+    assert call("polymul_negacyclic", A, B, B + nbytes - 4, n, 17, batch, None) == EALIAS
+    assert call("polymul_negacyclic", A, B, A - nbytes + 4, n, 17, batch, None) == EALIAS
+    assert call("polymul_negacyclic_plain", A, B, B, n, 17, batch, None) == EALIAS
+    assert call("polymul_negacyclic_u64", A, B, A + 8, n, 17, batch, None) == EALIAS
+
+
+def test_size_overflow():
+    assert call("polymul_negacyclic", A, B, C, 65536, 17, 1 << 50, None) == EINVAL
+
+
+def test_rns_arguments():
+    qs = (ctypes.c_uint32 * 2)(17, 1)
+    assert call("polymul_negacyclic_rns", A, B, C, 256, ctypes.cast(qs, ctypes.c_void_p), 2, 1, None) == EINVAL
+    qs = (ctypes.c_uint32 * 2)(17, 19)
+    assert call("polymul_negacyclic_rns", A, B, C, 256, ctypes.cast(qs, ctypes.c_void_p), 0, 1, None) == EINVAL
+    assert call("polymul_negacyclic_rns", A, B, C, 256, None, 2, 1, None) == EINVAL
+    assert call("polymul_negacyclic_rns", A, B, A, 256, ctypes.cast(qs, ctypes.c_void_p), 2, 1, None) == EALIAS
+    assert call("polymul_negacyclic_rns", None, None, None, 256, ctypes.cast(qs, ctypes.c_void_p), 2, 0, None) == 0
+
+
+def test_plan_arguments():
+    h = ctypes.c_void_p()
+    assert call("polymul_plan_create", None, None, 0, 0) == EINVAL
+    assert call("polymul_plan_execute", None, None) == EINVAL
+    assert call("polymul_plan_destroy", None) == 0
+
+
+def test_binding_refuses_host_tensors():
+    import torch
+    with pytest.raises(TypeError):
+        pm.polymul_negacyclic(torch.zeros(4, dtype=torch.int32), torch.zeros(4, dtype=torch.int32), 17)
