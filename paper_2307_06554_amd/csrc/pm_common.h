@@ -45,7 +45,7 @@ struct ModQ32 {
   uint64_t mu;      // floor(2^64 / q) for Barrett reduction (q >= 2)
   uint64_t lift;    // multiple of q in [2^62, 2^62 + q): makes |x| < 2^62 non-negative
   uint32_t r64;     // 2^64 mod q
-  uint32_t pad;
+  uint32_t m32;     // floor(2^32 / q), for reducing 32-bit words
 };
 
 inline ModQ32 make_mod32(uint32_t q, int L) {
@@ -62,6 +62,8 @@ inline ModQ32 make_mod32(uint32_t q, int L) {
   m.lift = k * q;
   unsigned __int128 t = ((unsigned __int128)1 << 64) % q;
   m.r64 = (uint32_t)t;
+  uint64_t m32 = ((uint64_t)1 << 32) / q;
+  m.m32 = m32 > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)m32;
   return m;
 }
 
@@ -73,6 +75,15 @@ __device__ __forceinline__ uint32_t reduce_u64(uint64_t x, const ModQ32& m) {
   if (r >= m.q) r -= m.q;
   if (r >= m.q) r -= m.q;
   return (uint32_t)r;
+}
+// x mod q for a 32-bit word: with m32 = floor(2^32/q) the estimate
+// floor(x*m32/2^32) is at most 2 below floor(x/q) and never above it.
+__device__ __forceinline__ uint32_t reduce_u32(uint32_t x, const ModQ32& m) {
+  uint32_t qe = __umulhi(x, m.m32);
+  uint32_t r = x - qe * m.q;
+  if (r >= m.q) r -= m.q;
+  if (r >= m.q) r -= m.q;
+  return r;
 }
 // Signed |x| < 2^62.
 __device__ __forceinline__ uint32_t reduce_i64(int64_t x, const ModQ32& m) {

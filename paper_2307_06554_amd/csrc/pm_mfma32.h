@@ -29,6 +29,7 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
 constexpr int kMaxQ = 16;  // moduli per launch (RNS channels are chunked above this)
+constexpr int kThreads = 256;  // threads per workgroup (4 waves)
 
 struct Mfma32Params {
   const uint32_t* a;
@@ -36,6 +37,7 @@ struct Mfma32Params {
   uint32_t* c;
   uint64_t nprod;        // products handled by this launch
   uint32_t n, t, r;      // n = t * r
+  uint32_t log2n;
   uint32_t log2t, log2spd, spd;  // K-steps of 32 per d: spd = max(1, t/32)
   uint32_t rowlen;       // bytes of one B row that are read (= 32 * spd)
   uint32_t tz, tu, log2U;  // output tiles of 32x32 per product: tz * tu = 2^log2U
@@ -47,65 +49,181 @@ struct Mfma32Params {
   // Product i of this launch is global product (i / lc) * nq_total + l0 + (i % lc)
   // and uses modulus mods[i % lc].
   uint32_t lc, nq_total, l0;
+  uint32_t fast_epilogue;  // 1: sum_s T_s * rcent[s] is known to stay below 2^62 in magnitude
   ModQ32 mods[kMaxQ];
+  int32_t rcent[kMaxQ][8];  // 2^(8s) mod q as a centred residue, s < 2L-1
 };
 
+// Byte i of each of the four digit words, packed into one word (byte k from w[k]).
+template <int L>
+__device__ __forceinline__ void transpose_store(uint8_t* base, uint32_t plane, uint32_t off, const uint32_t (&w)[4]) {
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    uint32_t v = ((w[0] >> (8 * i)) & 0xFF) | (((w[1] >> (8 * i)) & 0xFF) << 8) |
+                 (((w[2] >> (8 * i)) & 0xFF) << 16) | (((w[3] >> (8 * i)) & 0xFF) << 24);
+    *(uint32_t*)(base + i * plane + off) = v;
+  }
+}
+
+// Stage the digit planes of one product into an LDS slot.
+//   A: reversed ext planes, position p holds ext[E - p] (ext[i] = a_i for i >= 0,
+//      -a_{n+i} for i < 0, zero outside (-n, n)).
+//   B: rows v in [v_lo, v_lo + b_rows): row v < r holds b[v t + w] for v >= 0 and
+//      -b[(v + r) t + w] for v < 0; rows v >= r and bytes w >= t are zero.
 template <int L>
 __device__ __forceinline__ void mfma32_stage(const Mfma32Params& P, uint8_t* slot, uint64_t gprod,
                                              const ModQ32& m, int v_lo) {
   const uint32_t* A = P.a + gprod * P.n;
   const uint32_t* B = P.b + gprod * P.n;
   const uint32_t q = m.q, thr = m.thr;
-  const int n = (int)P.n;
-  // Reversed ext planes: position p holds ext[E - p].
+  const int n = (int)P.n, t = (int)P.t, r = (int)P.r;
   const int a_dw = (int)(P.a_plane >> 2);
+  uint8_t* bbase = slot + L * P.a_plane;
+  const int row_dw = (int)(P.rowlen >> 2);
+  if (n >= 4) {
+    // E + 1 is a multiple of 4, so dword dw holds ext[4m .. 4m+3] reversed, m = (E+1)/4 - 1 - dw,
+    // and (since n is a multiple of 4) each group is wholly positive, negative or zero.
+    // All global loads of a pass are issued before any of them is used.
+    constexpr int kUnroll = 4;
+    const int mtop = (int)((P.E + 1) >> 2) - 1;
+    for (int base = 0; base < a_dw; base += kUnroll * kThreads) {
+      uint4 x[kUnroll];
+      int kind[kUnroll];
+#pragma unroll
+      for (int k = 0; k < kUnroll; ++k) {
+        const int dw = base + k * kThreads + (int)threadIdx.x;
+        const int i0 = 4 * (mtop - dw);
+        kind[k] = 0;
+        x[k] = make_uint4(0, 0, 0, 0);
+        if (dw < a_dw) {
+          if (i0 >= 0 && i0 < n) { kind[k] = 1; x[k] = *(const uint4*)(A + i0); }
+          else if (i0 < 0 && i0 >= -n) { kind[k] = 2; x[k] = *(const uint4*)(A + n + i0); }
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < kUnroll; ++k) {
+        const int dw = base + k * kThreads + (int)threadIdx.x;
+        if (dw >= a_dw) continue;
+        const uint32_t xr[4] = {reduce_u32(x[k].w, m), reduce_u32(x[k].z, m), reduce_u32(x[k].y, m),
+                                reduce_u32(x[k].x, m)};
+        uint32_t w[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          w[j] = kind[k] == 1 ? digits32<L>(xr[j], q, thr) : kind[k] == 2 ? neg_digits32<L>(xr[j], q, thr) : 0u;
+        transpose_store<L>(slot, P.a_plane, dw * 4, w);
+      }
+    }
+    // Source rows: each b word lands in row vs (+) and row vs - r (-) when staged.
+    const int src = r * row_dw;
+    for (int base = 0; base < src; base += kUnroll * kThreads) {
+      uint4 x[kUnroll];
+#pragma unroll
+      for (int k = 0; k < kUnroll; ++k) {
+        const int e = base + k * kThreads + (int)threadIdx.x;
+        const int vs = e / row_dw, wd = e - vs * row_dw;
+        x[k] = make_uint4(0, 0, 0, 0);
+        if (e < src && 4 * wd < t) x[k] = *(const uint4*)(B + vs * t + 4 * wd);
+      }
+#pragma unroll
+      for (int k = 0; k < kUnroll; ++k) {
+        const int e = base + k * kThreads + (int)threadIdx.x;
+        if (e >= src) continue;
+        const int vs = e / row_dw, wd = e - vs * row_dw;
+        const int rp = vs - v_lo, rn = vs - r - v_lo;
+        const uint32_t xr[4] = {reduce_u32(x[k].x, m), reduce_u32(x[k].y, m), reduce_u32(x[k].z, m),
+                                reduce_u32(x[k].w, m)};
+        uint32_t w[4], nw[4];
+        const bool live = 4 * wd < t;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          w[j] = live ? digits32<L>(xr[j], q, thr) : 0u;
+          nw[j] = live ? neg_digits32<L>(xr[j], q, thr) : 0u;
+        }
+        if (rp >= 0 && rp < (int)P.b_rows) transpose_store<L>(bbase, P.b_plane, rp * P.b_rowstride + wd * 4, w);
+        if (rn >= 0 && rn < (int)P.b_rows) transpose_store<L>(bbase, P.b_plane, rn * P.b_rowstride + wd * 4, nw);
+      }
+    }
+    // Zero rows past the product (v >= r) inside the staged range.
+    const int z0 = max(0, r - v_lo);
+    const int nz = ((int)P.b_rows - z0) * row_dw;
+    for (int e = threadIdx.x; e < nz; e += blockDim.x) {
+      const int row = z0 + e / row_dw, wd = e % row_dw;
+      const uint32_t w[4] = {0, 0, 0, 0};
+      transpose_store<L>(bbase, P.b_plane, row * P.b_rowstride + wd * 4, w);
+    }
+    return;
+  }
+  // n < 4: byte-wise staging.
   for (int dw = threadIdx.x; dw < a_dw; dw += blockDim.x) {
     uint32_t w[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      int idx = (int)P.E - (dw * 4 + k);
+      const int idx = (int)P.E - (dw * 4 + k);
       uint32_t dg = 0;
-      if (idx >= 0 && idx < n) dg = digits32<L>(reduce_u64(A[idx], m), q, thr);
-      else if (idx < 0 && idx > -n) dg = neg_digits32<L>(reduce_u64(A[n + idx], m), q, thr);
+      if (idx >= 0 && idx < n) dg = digits32<L>(reduce_u32(A[idx], m), q, thr);
+      else if (idx < 0 && idx > -n) dg = neg_digits32<L>(reduce_u32(A[n + idx], m), q, thr);
       w[k] = dg;
     }
-#pragma unroll
-    for (int i = 0; i < L; ++i) {
-      uint32_t v = ((w[0] >> (8 * i)) & 0xFF) | (((w[1] >> (8 * i)) & 0xFF) << 8) |
-                   (((w[2] >> (8 * i)) & 0xFF) << 16) | (((w[3] >> (8 * i)) & 0xFF) << 24);
-      *(uint32_t*)(slot + i * P.a_plane + dw * 4) = v;
-    }
+    transpose_store<L>(slot, P.a_plane, dw * 4, w);
   }
-  // B rows v in [v_lo, v_lo + b_rows): v in [0, r) -> b[v t + w]; v < 0 -> -b[(v+r) t + w];
-  // v >= r or w >= t -> 0 (padding of a tile wider than the product).
-  uint8_t* bbase = slot + L * P.a_plane;
-  const int row_dw = (int)(P.rowlen >> 2);
   const int nb = (int)P.b_rows * row_dw;
-  const int t = (int)P.t, r = (int)P.r;
   for (int e = threadIdx.x; e < nb; e += blockDim.x) {
-    int row = e / row_dw, wd = e - row * row_dw;
-    int v = v_lo + row;
+    const int row = e / row_dw, wd = e - row * row_dw;
+    const int v = v_lo + row;
     uint32_t w[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      int ww = wd * 4 + k;
+      const int ww = wd * 4 + k;
       uint32_t dg = 0;
       if (ww < t) {
-        if (v >= 0 && v < r) dg = digits32<L>(reduce_u64(B[v * t + ww], m), q, thr);
-        else if (v < 0 && v > -r) dg = neg_digits32<L>(reduce_u64(B[(v + r) * t + ww], m), q, thr);
+        if (v >= 0 && v < r) dg = digits32<L>(reduce_u32(B[v * t + ww], m), q, thr);
+        else if (v < 0 && v > -r) dg = neg_digits32<L>(reduce_u32(B[(v + r) * t + ww], m), q, thr);
       }
       w[k] = dg;
     }
-#pragma unroll
-    for (int i = 0; i < L; ++i) {
-      uint32_t val = ((w[0] >> (8 * i)) & 0xFF) | (((w[1] >> (8 * i)) & 0xFF) << 8) |
-                     (((w[2] >> (8 * i)) & 0xFF) << 16) | (((w[3] >> (8 * i)) & 0xFF) << 24);
-      *(uint32_t*)(bbase + i * P.b_plane + row * P.b_rowstride + wd * 4) = val;
-    }
+    transpose_store<L>(bbase, P.b_plane, row * P.b_rowstride + wd * 4, w);
   }
 }
 
+// LDS reads of one K-step: five dwords around each limb's 16-byte A run
+// (starting at byte S, any alignment) and each limb's 16-byte B run.
+template <int L>
+__device__ __forceinline__ void araw_load(uint32_t (&x)[L][5], const uint8_t* aplane, uint32_t a_plane, int S) {
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    const uint32_t* p = (const uint32_t*)(aplane + i * a_plane) + (S >> 2);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) x[i][k] = p[k];
+  }
+}
+template <int L>
+__device__ __forceinline__ void b_load(v4i (&b)[L], const uint8_t* bplane, uint32_t b_plane, int boff) {
+#pragma unroll
+  for (int j = 0; j < L; ++j) b[j] = *(const v4i*)(bplane + j * b_plane + boff);
+}
+template <int L>
+__device__ __forceinline__ void a_align(v4i (&a)[L], const uint32_t (&x)[L][5], uint32_t sh) {
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    a[i][0] = (int)__builtin_amdgcn_alignbyte(x[i][1], x[i][0], sh);
+    a[i][1] = (int)__builtin_amdgcn_alignbyte(x[i][2], x[i][1], sh);
+    a[i][2] = (int)__builtin_amdgcn_alignbyte(x[i][3], x[i][2], sh);
+    a[i][3] = (int)__builtin_amdgcn_alignbyte(x[i][4], x[i][3], sh);
+  }
+}
+template <int L>
+__device__ __forceinline__ void mfma_block(v16i (&acc)[2 * L - 1], const v4i (&a)[L], const v4i (&b)[L]) {
+#pragma unroll
+  for (int i = 0; i < L; ++i)
+#pragma unroll
+    for (int j = 0; j < L; ++j)
+      acc[i + j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], b[j], acc[i + j], 0, 0, 0);
+}
+
 // One 32x32 output tile of one product: the whole K loop for all L*L limb pairs.
+// Per step: byte-align this step's A runs (their reads landed during the
+// previous step), issue the next step's reads into the freed registers, then
+// run this step's L*L MFMAs.  B alternates between two register sets.
 template <int L>
 __device__ __forceinline__ void mfma32_tile(const Mfma32Params& P, const uint8_t* slot, int z0, int u0,
                                             int v_lo, v16i (&acc)[2 * L - 1]) {
@@ -118,104 +236,251 @@ __device__ __forceinline__ void mfma32_tile(const Mfma32Params& P, const uint8_t
   // B: lane reads row (u - d) - v_lo, bytes w0 + 16 g .. + 15.
   const int B0 = (u0 + zl - v_lo) * (int)P.b_rowstride + 16 * g;
   const int steps = (int)(P.r << P.log2spd);
+  const int rs = (int)P.b_rowstride;
+  const uint32_t a_plane = P.a_plane, b_plane = P.b_plane;
 #pragma unroll
   for (int s = 0; s < 2 * L - 1; ++s) acc[s] = v16i{};
+  auto S_of = [&](int st) { return S0 - ((st >> P.log2spd) << P.log2t) + ((st & (P.spd - 1)) << 5); };
+  auto B_of = [&](int st) { return B0 - (st >> P.log2spd) * rs + ((st & (P.spd - 1)) << 5); };
 
-  for (int st = 0; st < steps; ++st) {
-    const int d = st >> P.log2spd;
-    const int w0 = (st & (P.spd - 1)) << 5;
-    const int S = S0 - (d << P.log2t) + w0;
-    const int boff = B0 - d * (int)P.b_rowstride + w0;
-    v4i af[L], bf[L];
-#pragma unroll
-    for (int i = 0; i < L; ++i) {
-      const uint32_t* p = (const uint32_t*)(aplane + i * P.a_plane) + (S >> 2);
-      uint32_t x0 = p[0], x1 = p[1], x2 = p[2], x3 = p[3], x4 = p[4];
-      const uint32_t sh = (uint32_t)(S & 3);
-      af[i][0] = (int)__builtin_amdgcn_alignbyte(x1, x0, sh);
-      af[i][1] = (int)__builtin_amdgcn_alignbyte(x2, x1, sh);
-      af[i][2] = (int)__builtin_amdgcn_alignbyte(x3, x2, sh);
-      af[i][3] = (int)__builtin_amdgcn_alignbyte(x4, x3, sh);
-      bf[i] = *(const v4i*)(bplane + i * P.b_plane + boff);
-    }
-#pragma unroll
-    for (int i = 0; i < L; ++i)
-#pragma unroll
-      for (int j = 0; j < L; ++j)
-        acc[i + j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[i], bf[j], acc[i + j], 0, 0, 0);
+  uint32_t araw[L][5];
+  v4i af[L], b0[L], b1[L];
+  int S = S_of(0);
+  araw_load<L>(araw, aplane, a_plane, S);
+  b_load<L>(b0, bplane, b_plane, B_of(0));
+  int st = 0;
+  for (; st + 2 < steps; st += 2) {
+    a_align<L>(af, araw, (uint32_t)(S & 3));
+    S = S_of(st + 1);
+    araw_load<L>(araw, aplane, a_plane, S);
+    b_load<L>(b1, bplane, b_plane, B_of(st + 1));
+    mfma_block<L>(acc, af, b0);
+    a_align<L>(af, araw, (uint32_t)(S & 3));
+    S = S_of(st + 2);
+    araw_load<L>(araw, aplane, a_plane, S);
+    b_load<L>(b0, bplane, b_plane, B_of(st + 2));
+    mfma_block<L>(acc, af, b1);
+  }
+  // one or two steps left
+  a_align<L>(af, araw, (uint32_t)(S & 3));
+  if (st + 1 < steps) {
+    S = S_of(st + 1);
+    araw_load<L>(araw, aplane, a_plane, S);
+    b_load<L>(b1, bplane, b_plane, B_of(st + 1));
+    mfma_block<L>(acc, af, b0);
+    a_align<L>(af, araw, (uint32_t)(S & 3));
+    mfma_block<L>(acc, af, b1);
+  } else {
+    mfma_block<L>(acc, af, b0);
   }
 }
 
+// Recombination c = sum_s T_s 2^(8s) mod q of the 16 outputs a lane holds, then
+// the stores.
 template <int L>
 __device__ __forceinline__ void mfma32_epilogue(const Mfma32Params& P, uint64_t gprod, const ModQ32& m,
-                                                int z0, int u0, const v16i (&acc)[2 * L - 1]) {
+                                                const int32_t* rc, int z0, int u0, const v16i (&acc)[2 * L - 1]) {
   const int lane = threadIdx.x & 63;
   const int g = lane >> 5;
   const int u = u0 + (lane & 31);
+  uint32_t out[16];
+#pragma unroll
+  for (int rr = 0; rr < 16; ++rr) {
+    if (P.fast_epilogue) {
+      // sum_s T_s * (2^(8s) mod q, centred) stays below 2^62 in magnitude (checked on the host).
+      int64_t x = 0;
+#pragma unroll
+      for (int s = 0; s < 2 * L - 1; ++s) x += (int64_t)acc[s][rr] * (int64_t)rc[s];
+      out[rr] = reduce_i64(x, m);
+    } else {
+      // Horner in radix 2^8 from the top shift class down.
+      uint32_t v = reduce_i64((int64_t)acc[2 * L - 2][rr], m);
+#pragma unroll
+      for (int s = 2 * L - 3; s >= 0; --s) v = reduce_i64((int64_t)v * 256 + (int64_t)acc[s][rr], m);
+      out[rr] = v;
+    }
+  }
   if (u >= (int)P.r) return;
   uint32_t* C = P.c + gprod * P.n;
 #pragma unroll
   for (int blk = 0; blk < 4; ++blk) {
     const int zb = z0 + 8 * blk + 4 * g;
-    uint32_t out[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int rr = blk * 4 + e;
-      // Horner in radix 2^8 from the top shift class down.
-      uint32_t v = reduce_i64((int64_t)acc[2 * L - 2][rr], m);
-#pragma unroll
-      for (int s = 2 * L - 3; s >= 0; --s) v = reduce_i64((int64_t)v * 256 + (int64_t)acc[s][rr], m);
-      out[e] = v;
-    }
     if (zb + 3 < (int)P.t) {
-      *(uint4*)(C + (size_t)u * P.t + zb) = make_uint4(out[0], out[1], out[2], out[3]);
+      *(uint4*)(C + (size_t)u * P.t + zb) = make_uint4(out[4 * blk], out[4 * blk + 1], out[4 * blk + 2], out[4 * blk + 3]);
     } else {
 #pragma unroll
       for (int e = 0; e < 4; ++e)
-        if (zb + e < (int)P.t) C[(size_t)u * P.t + zb + e] = out[e];
+        if (zb + e < (int)P.t) C[(size_t)u * P.t + zb + e] = out[4 * blk + e];
     }
   }
 }
 
-template <int L>
-__global__ __launch_bounds__(256) void mfma32_resident_kernel(const Mfma32Params P) {
-  extern __shared__ __align__(16) uint8_t smem[];
-  const uint32_t U = 1u << P.log2U;
-  const uint64_t unit0 = (uint64_t)blockIdx.x * 4;
-  const uint64_t first = unit0 >> P.log2U;  // first product of this workgroup
-  const uint64_t total_units = P.nprod << P.log2U;
-  // u-range covered by this workgroup inside each staged product.
-  int ut_lo, ut_hi;
-  if (U >= 4) {
-    const uint32_t t0 = (uint32_t)(unit0 & (U - 1));
-    ut_lo = (int)(t0 / P.tz);
-    ut_hi = (int)((t0 + 3) / P.tz);
-  } else {
-    ut_lo = 0;
-    ut_hi = (int)P.tu - 1;
-  }
-  const int v_lo = 32 * ut_lo - ((int)P.r - 1);
+// ---------------------------------------------------------------------------
+// Workgroup = group of 4 output tiles (grp*4 .. grp*4+3 over (product, tile)).
+// Staging items of one group (n >= 4): per staged product, n/4 A items (a word
+// group a[4m..4m+3] -> reversed dword E/4 - m, and its negated copy n/4 dwords
+// further) and n/4 B items (b[vs t + 4wd ..] -> row vs (+) and row vs - r (-)).
+// ---------------------------------------------------------------------------
+constexpr int kPrefetch = 8;  // uint4 loads in flight per thread during staging
 
-  for (uint32_t k = 0; k < P.slots; ++k) {
-    const uint64_t prod = first + k;
-    if (prod >= P.nprod) break;
-    const uint32_t li = (uint32_t)(prod % P.lc);
-    const uint64_t gprod = (prod / P.lc) * P.nq_total + P.l0 + li;
-    mfma32_stage<L>(P, smem + k * P.slot_bytes, gprod, P.mods[li], v_lo);
+struct GroupInfo {
+  uint64_t first;     // first product of the group
+  uint32_t nslots;    // products staged
+  int v_lo;           // first staged B row
+  uint64_t gp[4];     // global product index of each staged slot
+  uint32_t li[4];     // modulus index of each staged slot
+};
+
+__device__ __forceinline__ uint64_t global_product(const Mfma32Params& P, uint64_t prod, uint32_t* li) {
+  *li = (uint32_t)(prod % P.lc);
+  return (prod / P.lc) * P.nq_total + P.l0 + *li;
+}
+
+// Slot-indexed fields by selects (a dynamic index would put the arrays in scratch).
+__device__ __forceinline__ uint64_t slot_gp(const GroupInfo& g, uint32_t s) {
+  return s == 0 ? g.gp[0] : s == 1 ? g.gp[1] : s == 2 ? g.gp[2] : g.gp[3];
+}
+__device__ __forceinline__ uint32_t slot_li(const GroupInfo& g, uint32_t s) {
+  return s == 0 ? g.li[0] : s == 1 ? g.li[1] : s == 2 ? g.li[2] : g.li[3];
+}
+
+__device__ __forceinline__ GroupInfo group_info(const Mfma32Params& P, uint64_t grp) {
+  GroupInfo gi;
+  const uint32_t U = 1u << P.log2U;
+  const uint64_t unit0 = grp * 4;
+  gi.first = unit0 >> P.log2U;
+  const uint64_t left = P.nprod - gi.first;
+  gi.nslots = left < P.slots ? (uint32_t)left : P.slots;
+  const int ut_lo = U >= 4 ? (int)((uint32_t)(unit0 & (U - 1)) / P.tz) : 0;
+  gi.v_lo = 32 * ut_lo - ((int)P.r - 1);
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    gi.gp[s] = 0;
+    gi.li[s] = 0;
+    if ((uint32_t)s < gi.nslots) gi.gp[s] = global_product(P, gi.first + s, &gi.li[s]);
+  }
+  return gi;
+}
+
+// Global address of item i of a group (n >= 4), or null past the end.
+__device__ __forceinline__ const uint4* item_src(const Mfma32Params& P, const GroupInfo& gi, uint32_t i) {
+  const uint32_t lper = P.log2n - 1, quarter = P.n >> 2;
+  const uint32_t s = i >> lper, j = i & ((1u << lper) - 1);
+  if (s >= gi.nslots) return nullptr;
+  const uint64_t gp = slot_gp(gi, s);
+  if (j < quarter) return (const uint4*)(P.a + gp * P.n) + j;
+  return (const uint4*)(P.b + gp * P.n) + (j - quarter);
+}
+
+template <int L>
+__device__ __forceinline__ void item_store(const Mfma32Params& P, const GroupInfo& gi, uint8_t* smem, uint32_t i,
+                                           uint4 x) {
+  const uint32_t lper = P.log2n - 1, quarter = P.n >> 2;
+  const uint32_t s = i >> lper, j = i & ((1u << lper) - 1);
+  const ModQ32& m = P.mods[slot_li(gi, s)];
+  const uint32_t q = m.q, thr = m.thr;
+  uint8_t* slot = smem + s * P.slot_bytes;
+  const uint32_t xr[4] = {reduce_u32(x.x, m), reduce_u32(x.y, m), reduce_u32(x.z, m), reduce_u32(x.w, m)};
+  uint32_t w[4], nw[4];
+  if (j < quarter) {
+    // reversed: byte k of dword (E+1)/4 - 1 - j holds ext[4j + 3 - k]
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      w[k] = digits32<L>(xr[3 - k], q, thr);
+      nw[k] = neg_digits32<L>(xr[3 - k], q, thr);
+    }
+    const uint32_t dw = ((P.E + 1) >> 2) - 1 - j;
+    transpose_store<L>(slot, P.a_plane, dw * 4, w);
+    const uint32_t dwn = dw + quarter;
+    if (dwn < (P.a_plane >> 2)) transpose_store<L>(slot, P.a_plane, dwn * 4, nw);
+  } else {
+    const uint32_t e = j - quarter;
+    const int vs = (int)(e >> (P.log2t - 2)), wd = (int)(e & ((P.t >> 2) - 1));
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      w[k] = digits32<L>(xr[k], q, thr);
+      nw[k] = neg_digits32<L>(xr[k], q, thr);
+    }
+    uint8_t* bbase = slot + L * P.a_plane;
+    const int rp = vs - gi.v_lo, rn = vs - (int)P.r - gi.v_lo;
+    if (rp >= 0 && rp < (int)P.b_rows) transpose_store<L>(bbase, P.b_plane, rp * P.b_rowstride + wd * 4, w);
+    if (rn >= 0 && rn < (int)P.b_rows) transpose_store<L>(bbase, P.b_plane, rn * P.b_rowstride + wd * 4, nw);
+  }
+}
+
+// Parts of the staged B rows that no item writes but valid outputs read: bytes
+// w in [t, rowlen) of rows v < r (only when t < 32).  Rows v >= r feed only
+// discarded output columns; they are cleared too so LDS content is deterministic.
+template <int L>
+__device__ __forceinline__ void stage_zero_fill(const Mfma32Params& P, const GroupInfo& gi, uint8_t* smem) {
+  const int row_dw = (int)(P.rowlen >> 2);
+  const int tq = (int)(P.t >> 2);
+  const int zr0 = max(0, (int)P.r - gi.v_lo);  // first row with v >= r
+  for (uint32_t s = 0; s < gi.nslots; ++s) {
+    uint8_t* bbase = smem + s * P.slot_bytes + L * P.a_plane;
+    if (tq < row_dw) {
+      const int pad = row_dw - tq;
+      const int cnt = zr0 < (int)P.b_rows ? zr0 * pad : (int)P.b_rows * pad;
+      for (int e = threadIdx.x; e < cnt; e += kThreads) {
+        const int row = e / pad, wd = tq + e % pad;
+#pragma unroll
+        for (int i = 0; i < L; ++i) *(uint32_t*)(bbase + i * P.b_plane + row * P.b_rowstride + wd * 4) = 0u;
+      }
+    }
+    const int nz = ((int)P.b_rows - zr0) * row_dw;
+    for (int e = threadIdx.x; e < nz; e += kThreads) {
+      const int row = zr0 + e / row_dw, wd = e % row_dw;
+#pragma unroll
+      for (int i = 0; i < L; ++i) *(uint32_t*)(bbase + i * P.b_plane + row * P.b_rowstride + wd * 4) = 0u;
+    }
+  }
+}
+
+// One group of four 32x32 tiles per workgroup.  SMALL: n < 4, staged byte by byte.
+template <int L, bool SMALL>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void mfma32_group_kernel(const Mfma32Params P) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const uint64_t total_units = P.nprod << P.log2U;
+  const uint32_t U = 1u << P.log2U;
+  const uint64_t grp = blockIdx.x;
+  const GroupInfo gi = group_info(P, grp);
+  if constexpr (SMALL) {
+    for (uint32_t s = 0; s < gi.nslots; ++s)
+      mfma32_stage<L>(P, smem + s * P.slot_bytes, slot_gp(gi, s), P.mods[slot_li(gi, s)], gi.v_lo);
+  } else {
+    // all loads of a pass are issued before any is converted
+    const uint32_t nitems = gi.nslots * (P.n >> 1);
+    for (uint32_t base = 0; base < nitems; base += kPrefetch * kThreads) {
+      uint4 pf[kPrefetch];
+#pragma unroll
+      for (int k = 0; k < kPrefetch; ++k) {
+        const uint32_t i = base + threadIdx.x + k * kThreads;
+        const uint4* src = i < nitems ? item_src(P, gi, i) : nullptr;
+        pf[k] = src ? *src : make_uint4(0, 0, 0, 0);
+      }
+#pragma unroll
+      for (int k = 0; k < kPrefetch; ++k) {
+        const uint32_t i = base + threadIdx.x + k * kThreads;
+        if (i < nitems) item_store<L>(P, gi, smem, i, pf[k]);
+      }
+    }
+    stage_zero_fill<L>(P, gi, smem);
   }
   __syncthreads();
-
-  const uint64_t unit = unit0 + (threadIdx.x >> 6);
+  const uint64_t unit = grp * 4 + (threadIdx.x >> 6);
   if (unit >= total_units) return;
   const uint64_t prod = unit >> P.log2U;
   const uint32_t tile = (uint32_t)(unit & (U - 1));
   const int zt = (int)(tile % P.tz), ut = (int)(tile / P.tz);
-  const uint32_t li = (uint32_t)(prod % P.lc);
-  const uint64_t gprod = (prod / P.lc) * P.nq_total + P.l0 + li;
-  const uint8_t* slot = smem + (uint32_t)(prod - first) * P.slot_bytes;
+  const uint32_t sl = (uint32_t)(prod - gi.first);
+  const uint8_t* slot = smem + sl * P.slot_bytes;
+  const int v_lo = gi.v_lo;
   v16i acc[2 * L - 1];
   mfma32_tile<L>(P, slot, 32 * zt, 32 * ut, v_lo, acc);
-  mfma32_epilogue<L>(P, gprod, P.mods[li], 32 * zt, 32 * ut, acc);
+  uint32_t li;
+  const uint64_t gprod = global_product(P, prod, &li);
+  mfma32_epilogue<L>(P, gprod, P.mods[li], P.rcent[li], 32 * zt, 32 * ut, acc);
 }
 
 }  // namespace pm

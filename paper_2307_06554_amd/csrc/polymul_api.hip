@@ -75,12 +75,30 @@ Geometry32 geometry32(uint32_t n, int L) {
 
 constexpr uint32_t kMaxLds = 160 * 1024;
 
-template <int L>
+// Compute units of the current device (cached per device).
+uint32_t device_cus() {
+  static std::mutex mu;
+  static int cached_dev = -1;
+  static uint32_t cached = 256;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return cached;
+  std::lock_guard<std::mutex> g(mu);
+  if (dev != cached_dev) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0) {
+      cached = (uint32_t)prop.multiProcessorCount;
+      cached_dev = dev;
+    }
+  }
+  return cached;
+}
+
+template <int L, bool SMALL>
 polymul_status launch_mfma32_L(Mfma32Params& P, const Geometry32& g, hipStream_t s) {
   static std::once_flag once;
   static hipError_t attr_err = hipSuccess;
   std::call_once(once, [] {
-    attr_err = hipFuncSetAttribute((const void*)mfma32_resident_kernel<L>,
+    attr_err = hipFuncSetAttribute((const void*)mfma32_group_kernel<L, SMALL>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds);
   });
   if (attr_err != hipSuccess) return POLYMUL_EDEVICE;
@@ -88,9 +106,11 @@ polymul_status launch_mfma32_L(Mfma32Params& P, const Geometry32& g, hipStream_t
   const uint32_t lds = P.slots * P.slot_bytes;
   if (lds > kMaxLds) return POLYMUL_EUNSUPPORTED;
   const uint64_t units = P.nprod << P.log2U;
-  const uint64_t blocks = (units + 3) / 4;
+  const uint64_t groups = (units + 3) / 4;
+  // Persistent grid: as many workgroups as fit at once (LDS- and register-bound).
+  uint64_t blocks = groups;
   if (blocks > 0x7FFFFFFFull) return POLYMUL_EUNSUPPORTED;
-  hipLaunchKernelGGL(mfma32_resident_kernel<L>, dim3((uint32_t)blocks), dim3(256), lds, s, P);
+  hipLaunchKernelGGL((mfma32_group_kernel<L, SMALL>), dim3((uint32_t)blocks), dim3(kThreads), lds, s, P);
   return launch_status();
 }
 
@@ -106,6 +126,7 @@ polymul_status run_mfma32(const uint32_t* a, const uint32_t* b, uint32_t* c, uin
   P.a = a; P.b = b; P.c = c;
   P.nprod = nprod;
   P.n = n; P.t = g.t; P.r = g.r;
+  P.log2n = (uint32_t)ilog2(n);
   P.log2t = (uint32_t)ilog2(g.t);
   P.spd = g.spd; P.log2spd = (uint32_t)ilog2(g.spd);
   P.rowlen = g.rowlen;
@@ -114,11 +135,29 @@ polymul_status run_mfma32(const uint32_t* a, const uint32_t* b, uint32_t* c, uin
   P.a_plane = g.a_plane; P.b_rows = g.b_rows; P.b_rowstride = g.b_rowstride; P.b_plane = g.b_plane;
   P.E = g.E;
   P.lc = lc; P.nq_total = nq_total; P.l0 = l0;
-  for (uint32_t i = 0; i < lc; ++i) P.mods[i] = make_mod32(qs[i], L);
+  // Epilogue choice: the one-reduction form needs sum_s P_s * n * 2^14 * |rcent_s| < 2^62,
+  // P_s = number of limb pairs (i, j) with i + j = s.
+  bool fast = true;
+  for (uint32_t i = 0; i < lc; ++i) {
+    P.mods[i] = make_mod32(qs[i], L);
+    unsigned __int128 bound = 0;
+    uint64_t pw = 1 % qs[i];
+    for (int s = 0; s < 2 * L - 1; ++s) {
+      int64_t c = (int64_t)pw;
+      if (pw > qs[i] / 2) c -= (int64_t)qs[i];
+      P.rcent[i][s] = (int32_t)c;
+      uint64_t pairs = (uint64_t)((s < L ? s : 2 * L - 2 - s) + 1);
+      bound += (unsigned __int128)pairs * n * 16384u * (uint64_t)(c < 0 ? -c : c);
+      pw = (pw * 256) % qs[i];
+    }
+    if (bound >= ((unsigned __int128)1 << 62)) fast = false;
+  }
+  P.fast_epilogue = fast ? 1u : 0u;
+  const bool small = n < 4;
   switch (L) {
-    case 2: return launch_mfma32_L<2>(P, g, s);
-    case 3: return launch_mfma32_L<3>(P, g, s);
-    default: return launch_mfma32_L<4>(P, g, s);
+    case 2: return small ? launch_mfma32_L<2, true>(P, g, s) : launch_mfma32_L<2, false>(P, g, s);
+    case 3: return small ? launch_mfma32_L<3, true>(P, g, s) : launch_mfma32_L<3, false>(P, g, s);
+    default: return small ? launch_mfma32_L<4, true>(P, g, s) : launch_mfma32_L<4, false>(P, g, s);
   }
 }
 
