@@ -16,8 +16,9 @@
  *   - Polynomials are stored lowest degree first, one machine word per
  *     coefficient (uint32_t for q < 2^32, uint64_t for q < 2^64), products
  *     laid out back to back: element [p][j] is at offset p*n + j.
- *   - a, b, c are DEVICE pointers owned by the caller.  The library never
- *     frees or retains them (plans keep the pointers they were given).
+ *   - a, b, c are DEVICE pointers owned by the caller, 16-byte aligned.  The
+ *     library never frees or retains them (plans keep the pointers they were
+ *     given).
  *   - Input words are read mod q (any 32/64-bit value is accepted); outputs
  *     are canonical, in [0, q).
  *   - n must be a power of two, 1 <= n <= 65536; q >= 2 (prime or not).

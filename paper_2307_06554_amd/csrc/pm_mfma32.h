@@ -211,19 +211,24 @@ __device__ __forceinline__ void a_align(v4i (&a)[L], const uint32_t (&x)[L][5], 
     a[i][3] = (int)__builtin_amdgcn_alignbyte(x[i][4], x[i][3], sh);
   }
 }
+// One K-step of L*L MFMAs, B limb (column) by column.  As soon as column j is
+// issued, b[j] takes the next step's read for limb j, which then has the rest
+// of this step to land.
 template <int L>
-__device__ __forceinline__ void mfma_block(v16i (&acc)[2 * L - 1], const v4i (&a)[L], const v4i (&b)[L]) {
+__device__ __forceinline__ void mfma_step(v16i (&acc)[2 * L - 1], const v4i (&a)[L], v4i (&b)[L],
+                                          const uint8_t* bplane, uint32_t b_plane, int boff_next, bool next) {
 #pragma unroll
-  for (int i = 0; i < L; ++i)
+  for (int j = 0; j < L; ++j) {
 #pragma unroll
-    for (int j = 0; j < L; ++j)
+    for (int i = 0; i < L; ++i)
       acc[i + j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], b[j], acc[i + j], 0, 0, 0);
+    if (next) b[j] = *(const v4i*)(bplane + j * b_plane + boff_next);
+  }
 }
 
 // One 32x32 output tile of one product: the whole K loop for all L*L limb pairs.
-// Per step: byte-align this step's A runs (their reads landed during the
-// previous step), issue the next step's reads into the freed registers, then
-// run this step's L*L MFMAs.  B alternates between two register sets.
+// Per step: byte-align the A runs read during the previous step, issue the next
+// step's A reads into the freed raw registers, then the MFMAs (which refill B).
 template <int L>
 __device__ __forceinline__ void mfma32_tile(const Mfma32Params& P, const uint8_t* slot, int z0, int u0,
                                             int v_lo, v16i (&acc)[2 * L - 1]) {
@@ -244,34 +249,16 @@ __device__ __forceinline__ void mfma32_tile(const Mfma32Params& P, const uint8_t
   auto B_of = [&](int st) { return B0 - (st >> P.log2spd) * rs + ((st & (P.spd - 1)) << 5); };
 
   uint32_t araw[L][5];
-  v4i af[L], b0[L], b1[L];
+  v4i af[L], b[L];
   int S = S_of(0);
   araw_load<L>(araw, aplane, a_plane, S);
-  b_load<L>(b0, bplane, b_plane, B_of(0));
-  int st = 0;
-  for (; st + 2 < steps; st += 2) {
+  b_load<L>(b, bplane, b_plane, B_of(0));
+  for (int st = 0; st < steps; ++st) {
+    const bool next = st + 1 < steps;  // uniform
     a_align<L>(af, araw, (uint32_t)(S & 3));
     S = S_of(st + 1);
-    araw_load<L>(araw, aplane, a_plane, S);
-    b_load<L>(b1, bplane, b_plane, B_of(st + 1));
-    mfma_block<L>(acc, af, b0);
-    a_align<L>(af, araw, (uint32_t)(S & 3));
-    S = S_of(st + 2);
-    araw_load<L>(araw, aplane, a_plane, S);
-    b_load<L>(b0, bplane, b_plane, B_of(st + 2));
-    mfma_block<L>(acc, af, b1);
-  }
-  // one or two steps left
-  a_align<L>(af, araw, (uint32_t)(S & 3));
-  if (st + 1 < steps) {
-    S = S_of(st + 1);
-    araw_load<L>(araw, aplane, a_plane, S);
-    b_load<L>(b1, bplane, b_plane, B_of(st + 1));
-    mfma_block<L>(acc, af, b0);
-    a_align<L>(af, araw, (uint32_t)(S & 3));
-    mfma_block<L>(acc, af, b1);
-  } else {
-    mfma_block<L>(acc, af, b0);
+    if (next) araw_load<L>(araw, aplane, a_plane, S);
+    mfma_step<L>(acc, af, b, bplane, b_plane, B_of(st + 1), next);
   }
 }
 

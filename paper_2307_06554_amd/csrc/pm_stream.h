@@ -1,0 +1,369 @@
+// K-streaming split-limb MFMA kernel: 64-bit moduli (up to 8 limbs) at every
+// degree, and 32-bit moduli at degrees too large to hold both operands in LDS.
+//
+// Same recast as the resident kernel (C[z][u] = sum_(d,w) A[z][(d,w)] B[(d,w)][u],
+// n = t*r, Eq. (3) Toeplitz tiles and the Sec. 2.5 block split), with t <= 64
+// and one workgroup per 64 (z) x 64 (u) block of one product.  The K loop runs
+// over d in chunks of dc values:
+//   - A (reversed ext window of the chunk) is double-buffered in LDS;
+//   - B rows v = u - d live in a ring of 128 rows indexed by v mod 128 (a chunk
+//     uses dc + 63 rows and the next chunk's dc new rows never collide);
+//   - the input words of chunk c+1 are loaded into registers before chunk c's
+//     MFMAs and converted into LDS after them.
+// Accumulator bound (K-split): a shift class holds at most L limb pairs of
+// |product| <= 2^14, so its int32 sum is exact for K <= (2^31-1) / (L 2^14);
+// the host sets flush_every so that every flush covers at most 16384 K values
+// for L <= 4 and 8192 for L <= 8.  A flush folds sum_s T_s 2^(8s) into a running
+// residue mod q with 128-bit arithmetic (Sec. 2.4 limbs recombined, then the
+// modular reduction the paper leaves to Barrett/Montgomery, Sec. 2.6).
+#pragma once
+#include "pm_common.h"
+#include "pm_wide.h"
+#include "pm_mfma32.h"
+
+namespace pm {
+
+constexpr int kMaxQS = 8;        // moduli per streaming launch
+constexpr int kRing = 128;       // B rows held in LDS
+constexpr int kStreamThreads = 256;
+
+struct StreamParams {
+  const void* a;
+  const void* b;
+  void* c;
+  uint64_t nprod;
+  uint32_t n, t, log2t, r;
+  uint32_t spd, log2spd, rowlen, rs;  // K-steps per d, bytes per B row read, row stride
+  uint32_t tz;            // 32-row z tiles in use (1 or 2)
+  uint32_t ublocks;       // 64-column workgroup blocks per product
+  uint32_t dc;            // d values per chunk
+  uint32_t nchunks;       // r / dc
+  uint32_t flush_every;   // chunks between int32 -> residue flushes
+  uint32_t a_win;         // bytes per limb of one A window buffer
+  uint32_t lds_b;         // LDS offset of the B ring
+  uint32_t lc, nq_total, l0;  // product i -> global (i/lc)*nq_total + l0 + i%lc, modulus i%lc
+  ModQ64 mods[kMaxQS];
+};
+
+template <typename W>
+__device__ __forceinline__ uint64_t word_reduce(W x, const ModQ64& m) {
+  if (sizeof(W) == 4) {
+    uint64_t v = (uint64_t)x;
+    return v < m.q ? v : mod_u64(v, m);
+  }
+  const uint64_t v = (uint64_t)x;
+  return v < m.q ? v : mod_u64(v, m);
+}
+
+// L digits of the residue x in [0, q), packed little-endian (digit i in byte i).
+template <int L>
+__device__ __forceinline__ uint64_t digits64(uint64_t x, const ModQ64& m) {
+  constexpr uint64_t B = limb_bias(L);
+  const uint64_t v = x <= m.thr ? x : x - m.q;  // wraps mod 2^64: the representative in W_L
+  return (v + B) ^ B;
+}
+template <int L>
+__device__ __forceinline__ uint64_t neg_digits64(uint64_t x, const ModQ64& m) {
+  return digits64<L>(x == 0 ? 0ull : m.q - x, m);
+}
+
+// Byte i of four packed digit words -> plane i, one dword per plane.
+template <int L>
+__device__ __forceinline__ void transpose_store64(uint8_t* base, uint32_t plane, uint32_t off, const uint64_t (&w)[4]) {
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    const uint32_t v = (uint32_t)((w[0] >> (8 * i)) & 0xFF) | ((uint32_t)((w[1] >> (8 * i)) & 0xFF) << 8) |
+                       ((uint32_t)((w[2] >> (8 * i)) & 0xFF) << 16) | ((uint32_t)((w[3] >> (8 * i)) & 0xFF) << 24);
+    *(uint32_t*)(base + i * plane + off) = v;
+  }
+}
+
+// Four consecutive words starting at element `idx` (idx a multiple of 4).
+template <typename W>
+struct Quad {
+  W w[4];
+};
+template <typename W>
+__device__ __forceinline__ Quad<W> load_quad(const W* p) {
+  Quad<W> q;
+  if (sizeof(W) == 4) {
+    const uint4 x = *(const uint4*)p;
+    q.w[0] = (W)x.x; q.w[1] = (W)x.y; q.w[2] = (W)x.z; q.w[3] = (W)x.w;
+  } else {
+    const uint4 x = *(const uint4*)p;
+    const uint4 y = *(const uint4*)(p + 2);
+    q.w[0] = (W)(((uint64_t)x.y << 32) | x.x);
+    q.w[1] = (W)(((uint64_t)x.w << 32) | x.z);
+    q.w[2] = (W)(((uint64_t)y.y << 32) | y.x);
+    q.w[3] = (W)(((uint64_t)y.w << 32) | y.z);
+  }
+  return q;
+}
+
+// Staging items of one workgroup.  An item is four consecutive words.
+//   A item m: ext[4m .. 4m+3] of the chunk window (a, -a wrapped, or zero).
+//   B item:   words w = 4k .. 4k+3 of source row v of the ring (b or -b or zero).
+struct StreamItem {
+  int kind;   // 0 none/zero, 1 A, 2 B
+  int e;      // A: group m; B: row v
+  int k;      // B: word group in the row
+};
+
+struct ChunkItems {
+  int a_groups;   // A groups of the window
+  int a_m0;       // first group index (lowest ext index / 4)
+  int b_rows;     // rows staged
+  int b_v0;       // first row
+  int row_groups; // word groups per row
+  __device__ __forceinline__ int count() const { return a_groups + b_rows * row_groups; }
+  __device__ __forceinline__ StreamItem item(int i) const {
+    StreamItem it;
+    if (i < a_groups) { it.kind = 1; it.e = a_m0 + i; it.k = 0; return it; }
+    i -= a_groups;
+    it.kind = 2;
+    it.e = b_v0 + i / row_groups;
+    it.k = i % row_groups;
+    return it;
+  }
+};
+
+__device__ __forceinline__ ChunkItems chunk_items(const StreamParams& P, int c, int U0, bool first) {
+  ChunkItems ci;
+  const int D0 = c * (int)P.dc;
+  const int I1 = (D0 + (int)P.dc - 1) * (int)P.t + 32 * (int)P.tz - 1;  // highest ext index of the window
+  ci.a_groups = (int)(P.a_win >> 2);
+  ci.a_m0 = ((I1 + 1) >> 2) - ci.a_groups;
+  ci.row_groups = (int)(P.rowlen >> 2);
+  if (first) {
+    ci.b_v0 = U0 - (int)P.dc + 1;
+    ci.b_rows = 63 + (int)P.dc;
+  } else {
+    ci.b_v0 = U0 - (c + 1) * (int)P.dc + 1;
+    ci.b_rows = (int)P.dc;
+  }
+  return ci;
+}
+
+// Global source of an item (nullptr: the item is all zeros).
+template <typename W>
+__device__ __forceinline__ const W* item_ptr(const StreamParams& P, const StreamItem& it, uint64_t gp, bool* neg) {
+  const int n = (int)P.n, t = (int)P.t, r = (int)P.r;
+  *neg = false;
+  if (it.kind == 1) {
+    const int i0 = 4 * it.e;
+    if (n < 4) return nullptr;  // handled element-wise
+    if (i0 >= 0 && i0 < n) return (const W*)P.a + gp * P.n + i0;
+    if (i0 < 0 && i0 >= -n) { *neg = true; return (const W*)P.a + gp * P.n + (n + i0); }
+    return nullptr;
+  }
+  if (it.kind == 2) {
+    const int v = it.e, w = 4 * it.k;
+    if (t < 4 || w >= t) return nullptr;
+    if (v >= 0 && v < r) return (const W*)P.b + gp * P.n + (size_t)v * t + w;
+    if (v < 0 && v > -r) { *neg = true; return (const W*)P.b + gp * P.n + (size_t)(v + r) * t + w; }
+  }
+  return nullptr;
+}
+
+// Convert one item (its four words already loaded, or element-wise for tiny n) and write it.
+template <int L, typename W>
+__device__ __forceinline__ void item_write(const StreamParams& P, const StreamItem& it, const Quad<W>& x, bool live,
+                                           bool neg, uint64_t gp, const ModQ64& m, uint8_t* abuf, uint8_t* ring,
+                                           int I1) {
+  uint64_t d[4] = {0, 0, 0, 0};
+  const int n = (int)P.n, t = (int)P.t, r = (int)P.r;
+  if (it.kind == 1) {
+    const int i0 = 4 * it.e;
+    if (n < 4) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int idx = i0 + k;
+        if (idx >= 0 && idx < n) d[k] = digits64<L>(word_reduce<W>(((const W*)P.a)[gp * P.n + idx], m), m);
+        else if (idx < 0 && idx > -n) d[k] = neg_digits64<L>(word_reduce<W>(((const W*)P.a)[gp * P.n + n + idx], m), m);
+      }
+    } else if (live) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint64_t xr = word_reduce<W>(x.w[k], m);
+        d[k] = neg ? neg_digits64<L>(xr, m) : digits64<L>(xr, m);
+      }
+    }
+    // reversed: position p = I1 - idx; byte j of dword (I1 - i0 - 3)/4 holds idx = i0 + 3 - j
+    const uint64_t w4[4] = {d[3], d[2], d[1], d[0]};
+    transpose_store64<L>(abuf, P.a_win, (uint32_t)(I1 - i0 - 3), w4);
+  } else if (it.kind == 2) {
+    const int v = it.e, w = 4 * it.k;
+    if (t < 4) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int ww = w + k;
+        if (ww >= t) continue;
+        if (v >= 0 && v < r) d[k] = digits64<L>(word_reduce<W>(((const W*)P.b)[gp * P.n + (size_t)v * t + ww], m), m);
+        else if (v < 0 && v > -r)
+          d[k] = neg_digits64<L>(word_reduce<W>(((const W*)P.b)[gp * P.n + (size_t)(v + r) * t + ww], m), m);
+      }
+    } else if (live) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint64_t xr = word_reduce<W>(x.w[k], m);
+        d[k] = neg ? neg_digits64<L>(xr, m) : digits64<L>(xr, m);
+      }
+    }
+    const uint32_t slot = (uint32_t)(v & (kRing - 1));
+    transpose_store64<L>(ring, kRing * P.rs, slot * P.rs + (uint32_t)w, d);
+  }
+}
+
+// Running residues: res = (res + sum_s T_s 2^(8s)) mod q, then T_s = 0.
+// sum_s T_s (2^(8s) mod q) is formed exactly as a signed 128-bit value
+// (|T_s| < 2^31, 2L-1 <= 15 terms of < 2^95 each) and reduced once.
+template <int L, typename W>
+__device__ __forceinline__ void stream_flush(v16i (&acc)[2 * L - 1], W (&res)[16], const ModQ64& m) {
+#pragma unroll
+  for (int rr = 0; rr < 16; ++rr) {
+    U128 x{0, 0};
+#pragma unroll
+    for (int s = 0; s < 2 * L - 1; ++s) {
+      const int32_t tv = acc[s][rr];
+      const U128 p = mul64x64((uint64_t)(tv < 0 ? -(int64_t)tv : (int64_t)tv), m.r[s]);
+      if (tv >= 0) x = add128(x, p);
+      else x = add128(x, U128{~p.lo + 1, ~p.hi + (p.lo == 0 ? 1u : 0u)});  // two's complement
+    }
+    const bool negative = (int64_t)x.hi < 0;
+    if (negative) x = U128{~x.lo + 1, ~x.hi + (x.lo == 0 ? 1u : 0u)};
+    uint64_t v = mod_u128(x.hi, x.lo, m);
+    if (negative && v) v = m.q - v;
+    res[rr] = (W)addmod64((uint64_t)res[rr], v, m.q);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+#pragma unroll
+  for (int s = 0; s < 2 * L - 1; ++s) acc[s] = v16i{};
+}
+
+template <int L, typename W, int WPE>
+__global__ __launch_bounds__(kStreamThreads) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
+void stream_kernel(const StreamParams P) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const uint64_t wg = blockIdx.x;
+  const uint64_t prod = wg / P.ublocks;
+  const int U0 = 64 * (int)(wg - prod * P.ublocks);
+  const uint32_t li = (uint32_t)(prod % P.lc);
+  const uint64_t gp = (prod / P.lc) * P.nq_total + P.l0 + li;
+  const ModQ64& m = P.mods[li];
+  uint8_t* ring = smem + P.lds_b;
+  const int wave = (int)(threadIdx.x >> 6);
+  const int lane = (int)(threadIdx.x & 63);
+  const int zt = wave & 1, ut = wave >> 1;
+  const bool active = zt < (int)P.tz;
+  const int z0 = 32 * zt, u0 = U0 + 32 * ut;
+  const int zl = lane & 31, g = lane >> 5;
+  const int t = (int)P.t, rs = (int)P.rs;
+
+  // ---- chunk 0: everything it needs, loaded synchronously
+  {
+    const ChunkItems ci = chunk_items(P, 0, U0, true);
+    const int I1 = ((int)P.dc - 1) * t + 32 * (int)P.tz - 1;
+    for (int i = threadIdx.x; i < ci.count(); i += kStreamThreads) {
+      const StreamItem it = ci.item(i);
+      bool neg;
+      const W* src = item_ptr<W>(P, it, gp, &neg);
+      Quad<W> x{};
+      if (src) x = load_quad<W>(src);
+      item_write<L, W>(P, it, x, src != nullptr, neg, gp, m, smem, ring, I1);
+    }
+  }
+  __syncthreads();
+
+  v16i acc[2 * L - 1];
+#pragma unroll
+  for (int s = 0; s < 2 * L - 1; ++s) acc[s] = v16i{};
+  W res[16];
+#pragma unroll
+  for (int rr = 0; rr < 16; ++rr) res[rr] = 0;
+
+  // per-lane A base: S = S_base + (dc - 1 - dl) t + w0 inside the chunk's window
+  const int S_base = 32 * (int)P.tz - 1 - z0 - zl + 16 * g;
+  constexpr int kItems = 3;  // items per thread carried over a chunk (dc <= 16, t <= 64)
+  const int steps = (int)(P.dc << P.log2spd);
+
+  for (int c = 0; c < (int)P.nchunks; ++c) {
+    // ---- issue the next chunk's loads
+    const bool more = c + 1 < (int)P.nchunks;
+    ChunkItems cn{};
+    Quad<W> pf[kItems];
+    bool pl[kItems], pn[kItems];
+    if (more) {
+      cn = chunk_items(P, c + 1, U0, false);
+#pragma unroll
+      for (int k = 0; k < kItems; ++k) {
+        const int i = (int)threadIdx.x + k * kStreamThreads;
+        pl[k] = false;
+        pn[k] = false;
+        if (i < cn.count()) {
+          const StreamItem it = cn.item(i);
+          const W* src = item_ptr<W>(P, it, gp, &pn[k]);
+          if (src) { pf[k] = load_quad<W>(src); pl[k] = true; }
+        }
+      }
+    }
+    // ---- this chunk's MFMAs
+    if (active) {
+      const uint8_t* abuf = smem + (c & 1) * (L * P.a_win);
+      const int D0 = c * (int)P.dc;
+      uint32_t araw[L][5];
+      v4i af[L], b[L];
+      auto S_of = [&](int st) {
+        const int dl = st >> P.log2spd;
+        return S_base + ((int)P.dc - 1 - dl) * t + ((st & ((int)P.spd - 1)) << 5);
+      };
+      auto B_of = [&](int st) {
+        const int d = D0 + (st >> P.log2spd);
+        return ((u0 + zl - d) & (kRing - 1)) * rs + ((st & ((int)P.spd - 1)) << 5) + 16 * g;
+      };
+      int S = S_of(0);
+      araw_load<L>(araw, abuf, P.a_win, S);
+      b_load<L>(b, ring, kRing * P.rs, B_of(0));
+      for (int st = 0; st < steps; ++st) {
+        const bool next = st + 1 < steps;
+        a_align<L>(af, araw, (uint32_t)(S & 3));
+        S = S_of(st + 1);
+        if (next) araw_load<L>(araw, abuf, P.a_win, S);
+        mfma_step<L>(acc, af, b, ring, kRing * P.rs, B_of(st + 1), next);
+      }
+      if (!more || (c + 1) % (int)P.flush_every == 0) stream_flush<L, W>(acc, res, m);
+    }
+    if (!more) break;
+    // ---- convert and write the next chunk (its A buffer and ring rows are not read now)
+    {
+      uint8_t* abuf_n = smem + ((c + 1) & 1) * (L * P.a_win);
+      const int I1n = ((c + 1) * (int)P.dc + (int)P.dc - 1) * t + 32 * (int)P.tz - 1;
+#pragma unroll
+      for (int k = 0; k < kItems; ++k) {
+        const int i = (int)threadIdx.x + k * kStreamThreads;
+        if (i < cn.count()) item_write<L, W>(P, cn.item(i), pf[k], pl[k], pn[k], gp, m, abuf_n, ring, I1n);
+      }
+      for (int i = (int)threadIdx.x + kItems * kStreamThreads; i < cn.count(); i += kStreamThreads) {
+        const StreamItem it = cn.item(i);
+        bool neg;
+        const W* src = item_ptr<W>(P, it, gp, &neg);
+        Quad<W> x{};
+        if (src) x = load_quad<W>(src);
+        item_write<L, W>(P, it, x, src != nullptr, neg, gp, m, abuf_n, ring, I1n);
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- store the residues: lane holds z = z0 + 8 blk + 4 g + e, u = u0 + zl
+  if (!active) return;
+  const int u = u0 + zl;
+  if (u >= (int)P.r) return;
+  W* C = (W*)P.c + gp * P.n;
+#pragma unroll
+  for (int rr = 0; rr < 16; ++rr) {
+    const int z = z0 + 8 * (rr >> 2) + 4 * g + (rr & 3);
+    if (z < t) C[(size_t)u * t + z] = res[rr];
+  }
+}
+
+}  // namespace pm

@@ -9,6 +9,8 @@
 #include "pm_common.h"
 #include "pm_mfma32.h"
 #include "pm_plain.h"
+#include "pm_stream.h"
+#include "pm_wide_host.h"
 
 using namespace pm;
 
@@ -33,6 +35,8 @@ polymul_status check_arrays(const void* a, const void* b, const void* c, uint64_
   if (!is_pow2(n) || n > 65536) return POLYMUL_EINVAL;
   if (batch == 0) { *bytes = 0; return POLYMUL_OK; }
   if (!a || !b || !c) return POLYMUL_EINVAL;
+  // word groups are moved with 16-byte loads and stores
+  if (((uintptr_t)a | (uintptr_t)b | (uintptr_t)c) & 15) return POLYMUL_EINVAL;
   unsigned __int128 total = (unsigned __int128)batch * words_per_item * n * elem;
   if (total >> 62) return POLYMUL_EINVAL;
   *bytes = (uint64_t)total;
@@ -115,9 +119,26 @@ polymul_status launch_mfma32_L(Mfma32Params& P, const Geometry32& g, hipStream_t
 }
 
 // nprod products (i -> global (i/lc)*nq_total + l0 + i%lc) with moduli qs[0..lc).
+template <typename W>
+polymul_status run_stream(const W* a, const W* b, W* c, uint32_t n, const uint64_t* qs, uint32_t lc,
+                          uint32_t nq_total, uint32_t l0, uint64_t nprod, hipStream_t s);
+
 polymul_status run_mfma32(const uint32_t* a, const uint32_t* b, uint32_t* c, uint32_t n, const uint32_t* qs,
                           uint32_t lc, uint32_t nq_total, uint32_t l0, uint64_t nprod, hipStream_t s) {
-  if (n > 8192) return POLYMUL_EUNSUPPORTED;
+  if (n > 8192) {
+    // degree too large for both operands in LDS: K-streaming kernel, moduli in chunks of kMaxQS
+    uint64_t q64[kMaxQ];
+    for (uint32_t i = 0; i < lc; ++i) q64[i] = qs[i];
+    if (lc <= (uint32_t)kMaxQS) return run_stream<uint32_t>(a, b, c, n, q64, lc, nq_total, l0, nprod, s);
+    // split the channel range (nprod = batch * lc)
+    const uint64_t batch = nprod / lc;
+    for (uint32_t c0 = 0; c0 < lc; c0 += kMaxQS) {
+      const uint32_t cc = lc - c0 < (uint32_t)kMaxQS ? lc - c0 : (uint32_t)kMaxQS;
+      polymul_status st = run_stream<uint32_t>(a, b, c, n, q64 + c0, cc, nq_total, l0 + c0, batch * cc, s);
+      if (st != POLYMUL_OK) return st;
+    }
+    return POLYMUL_OK;
+  }
   int L = 1;
   for (uint32_t i = 0; i < lc; ++i) L = L > limbs_for_q32(qs[i]) ? L : limbs_for_q32(qs[i]);
   if (L < 2) L = 2;
@@ -159,6 +180,62 @@ polymul_status run_mfma32(const uint32_t* a, const uint32_t* b, uint32_t* c, uin
     case 3: return small ? launch_mfma32_L<3, true>(P, g, s) : launch_mfma32_L<3, false>(P, g, s);
     default: return small ? launch_mfma32_L<4, true>(P, g, s) : launch_mfma32_L<4, false>(P, g, s);
   }
+}
+
+// ------------------------------------------------------- streaming kernel
+template <int L, typename W, int WPE>
+polymul_status launch_stream_L(const StreamParams& P, uint32_t lds, uint64_t blocks, hipStream_t s) {
+  static std::once_flag once;
+  static hipError_t attr_err = hipSuccess;
+  std::call_once(once, [] {
+    attr_err = hipFuncSetAttribute((const void*)stream_kernel<L, W, WPE>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds);
+  });
+  if (attr_err != hipSuccess) return POLYMUL_EDEVICE;
+  hipLaunchKernelGGL((stream_kernel<L, W, WPE>), dim3((uint32_t)blocks), dim3(kStreamThreads), lds, s, P);
+  return launch_status();
+}
+
+// nprod products of degree bound n (i -> global (i/lc)*nq_total + l0 + i%lc), moduli qs[0..lc).
+template <typename W>
+polymul_status run_stream(const W* a, const W* b, W* c, uint32_t n, const uint64_t* qs, uint32_t lc,
+                          uint32_t nq_total, uint32_t l0, uint64_t nprod, hipStream_t s) {
+  int L = 1;
+  for (uint32_t i = 0; i < lc; ++i) {
+    const int li = limbs_for_q64(qs[i]);
+    L = L > li ? L : li;
+  }
+  if (L < 2) L = 2;
+  if (sizeof(W) == 4 && L > 4) return POLYMUL_EINVAL;
+  L = L <= 4 ? 4 : 8;  // two instantiations: up to 4 and up to 8 limbs
+  StreamParams P{};
+  P.a = a; P.b = b; P.c = c;
+  P.nprod = nprod;
+  P.n = n;
+  P.t = n < 64 ? n : 64;
+  P.log2t = (uint32_t)ilog2(P.t);
+  P.r = n / P.t;
+  P.spd = P.t >= 64 ? 2 : 1;
+  P.log2spd = P.spd == 2 ? 1 : 0;
+  P.rowlen = 32 * P.spd;
+  P.rs = ((P.rowlen / 16) & 1) ? P.rowlen : P.rowlen + 16;
+  P.tz = (P.t + 31) / 32;
+  P.ublocks = (P.r + 63) / 64;
+  P.dc = P.r < 16 ? P.r : 16;
+  P.nchunks = P.r / P.dc;
+  const uint32_t kflush = L <= 4 ? 16384u : 8192u;  // K values per exact int32 class sum
+  uint32_t fe = kflush / (P.dc * P.t);
+  P.flush_every = fe < 1 ? 1 : fe;
+  P.a_win = ((P.dc - 1) * P.t + 32 * P.tz + P.rowlen + 4 + 15) & ~15u;
+  P.lds_b = 2u * (uint32_t)L * P.a_win;
+  const uint32_t lds = P.lds_b + (uint32_t)L * kRing * P.rs;
+  if (lds > kMaxLds) return POLYMUL_EUNSUPPORTED;
+  P.lc = lc; P.nq_total = nq_total; P.l0 = l0;
+  for (uint32_t i = 0; i < lc; ++i) P.mods[i] = make_mod64(qs[i], L);
+  const uint64_t blocks = nprod * P.ublocks;
+  if (blocks > 0x7FFFFFFFull) return POLYMUL_EUNSUPPORTED;
+  if (L == 4) return launch_stream_L<4, W, 2>(P, lds, blocks, s);
+  return launch_stream_L<8, W, 1>(P, lds, blocks, s);
 }
 
 }  // namespace
@@ -224,8 +301,7 @@ polymul_status polymul_negacyclic_u64(const uint64_t* a, const uint64_t* b, uint
   uint64_t bytes;
   polymul_status st = check_arrays(a, b, c, n, batch, 1, 8, &bytes);
   if (st != POLYMUL_OK || batch == 0) return st;
-  (void)stream;
-  return POLYMUL_EUNSUPPORTED;
+  return run_stream<uint64_t>(a, b, c, (uint32_t)n, &q, 1, 1, 0, batch, stream);
 }
 
 struct polymul_plan {

@@ -80,10 +80,15 @@ def test_aliasing_is_rejected():
     n, batch = 256, 4
     nbytes = n * batch * 4
     assert call("polymul_negacyclic", A, B, A, n, 17, batch, None) == EALIAS
-    assert call("polymul_negacyclic", A, B, B + nbytes - 4, n, 17, batch, None) == EALIAS
-    assert call("polymul_negacyclic", A, B, A - nbytes + 4, n, 17, batch, None) == EALIAS
+    assert call("polymul_negacyclic", A, B, B + nbytes - 16, n, 17, batch, None) == EALIAS
+    assert call("polymul_negacyclic", A, B, A - nbytes + 16, n, 17, batch, None) == EALIAS
     assert call("polymul_negacyclic_plain", A, B, B, n, 17, batch, None) == EALIAS
-    assert call("polymul_negacyclic_u64", A, B, A + 8, n, 17, batch, None) == EALIAS
+    assert call("polymul_negacyclic_u64", A, B, A + 16, n, 17, batch, None) == EALIAS
+
+
+def test_misaligned_pointers():
+    assert call("polymul_negacyclic", A + 4, B, C, 256, 17, 1, None) == EINVAL
+    assert call("polymul_negacyclic_u64", A, B, C + 8, 256, 17, 1, None) == EINVAL
 
 
 def test_size_overflow():
