@@ -89,7 +89,9 @@ polymul_status polymul_negacyclic_plain(const uint32_t* a, const uint32_t* b, ui
 /*
  * Grouped products of uneven size in one persistent launch, replayed from a
  * HIP graph (paper Sec. 2.6-2.7: parameters fixed once per configuration,
- * Algorithm 1's GenConfig/ExtractDimensions done at plan time).
+ * Algorithm 1's GenConfig/ExtractDimensions done at plan time).  All 32-bit
+ * groups share one persistent launch that takes work items largest first from
+ * an atomic queue; 64-bit groups add one streaming launch each to the graph.
  *
  * Group g holds `count` independent products of degree bound n over Z_q:
  *   a, b, c: device, count*n words of elem_bytes (4: q < 2^32; 8: q < 2^64).
@@ -117,6 +119,20 @@ polymul_status polymul_plan_create(polymul_plan** plan, const polymul_group* gro
                                    uint32_t ngroups, uint32_t flags);
 polymul_status polymul_plan_execute(polymul_plan* plan, hipStream_t stream);
 polymul_status polymul_plan_destroy(polymul_plan* plan);
+
+/*
+ * Tile table of the LDS-resident 32-bit path (paper Sec. 2.6, matrix dimension
+ * selection: the best block size is found by experiment).  For degree bound n
+ * and limb count L (1..4), t is the side of the Toeplitz tiles the product is
+ * cut into (n = t * r): n itself when n <= 32, otherwise a power of two in
+ * [32, min(n, 128)].  t = 0 restores the built-in choice.  The table is
+ * process-wide; the autotuner (paper_2307_06554_amd/tune.py) times the
+ * candidates on the GPU and calls polymul_tune_set with the winners.  Takes
+ * effect for launches and plans created afterwards.  No HIP call is made.
+ * EINVAL: bad n, L or t; EUNSUPPORTED: the tile does not fit in LDS.
+ */
+polymul_status polymul_tune_set(uint64_t n, uint32_t L, uint32_t t);
+polymul_status polymul_tune_get(uint64_t n, uint32_t L, uint32_t* t);
 
 #ifdef __cplusplus
 }

@@ -16,5 +16,7 @@ from .binding import (  # noqa: F401
     polymul_plan_destroy,
     polymul_plan_execute,
     polymul_status_string,
+    polymul_tune_get,
+    polymul_tune_set,
     Plan,
 )

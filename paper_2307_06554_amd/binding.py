@@ -28,6 +28,8 @@ _SIGNATURES = {
     "polymul_plan_create": (ctypes.c_int, [ctypes.POINTER(_vp), _vp, _u32, _u32]),
     "polymul_plan_execute": (ctypes.c_int, [_vp, _vp]),
     "polymul_plan_destroy": (ctypes.c_int, [_vp]),
+    "polymul_tune_set": (ctypes.c_int, [_u64, _u32, _u32]),
+    "polymul_tune_get": (ctypes.c_int, [_u64, _u32, ctypes.POINTER(_u32)]),
 }
 
 
@@ -172,6 +174,17 @@ def polymul_plan_execute(plan, stream=None):
 
 def polymul_plan_destroy(plan):
     _check(load_library().polymul_plan_destroy(plan), "polymul_plan_destroy")
+
+
+def polymul_tune_set(n, L, t):
+    """Set the Toeplitz tile side of the resident 32-bit path for (n, L); 0 = built-in."""
+    _check(load_library().polymul_tune_set(int(n), int(L), int(t)), "polymul_tune_set")
+
+
+def polymul_tune_get(n, L):
+    out = ctypes.c_uint32()
+    _check(load_library().polymul_tune_get(int(n), int(L), ctypes.byref(out)), "polymul_tune_get")
+    return out.value
 
 
 class Plan:

@@ -423,14 +423,13 @@ __device__ __forceinline__ void stage_zero_fill(const Mfma32Params& P, const Gro
   }
 }
 
-// One group of four 32x32 tiles per workgroup.  SMALL: n < 4, staged byte by byte.
+// One group of four 32x32 tiles: stage the products it touches, then each wave
+// runs its tile.  SMALL: n < 4, staged byte by byte.  Ends with every wave
+// past its last LDS read only if the caller synchronises afterwards.
 template <int L, bool SMALL>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
-void mfma32_group_kernel(const Mfma32Params P) {
-  extern __shared__ __align__(16) uint8_t smem[];
+__device__ __forceinline__ void resident_group(const Mfma32Params& P, uint64_t grp, uint8_t* smem) {
   const uint64_t total_units = P.nprod << P.log2U;
   const uint32_t U = 1u << P.log2U;
-  const uint64_t grp = blockIdx.x;
   const GroupInfo gi = group_info(P, grp);
   if constexpr (SMALL) {
     for (uint32_t s = 0; s < gi.nslots; ++s)
@@ -468,6 +467,14 @@ void mfma32_group_kernel(const Mfma32Params P) {
   uint32_t li;
   const uint64_t gprod = global_product(P, prod, &li);
   mfma32_epilogue<L>(P, gprod, P.mods[li], P.rcent[li], 32 * zt, 32 * ut, acc);
+}
+
+// One group of four 32x32 tiles per workgroup.
+template <int L, bool SMALL>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void mfma32_group_kernel(const Mfma32Params P) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  resident_group<L, SMALL>(P, blockIdx.x, smem);
 }
 
 }  // namespace pm

@@ -240,11 +240,10 @@ __device__ __forceinline__ void stream_flush(v16i (&acc)[2 * L - 1], W (&res)[16
   for (int s = 0; s < 2 * L - 1; ++s) acc[s] = v16i{};
 }
 
-template <int L, typename W, int WPE>
-__global__ __launch_bounds__(kStreamThreads) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
-void stream_kernel(const StreamParams P) {
-  extern __shared__ __align__(16) uint8_t smem[];
-  const uint64_t wg = blockIdx.x;
+// One 64 (z) x 64 (u) block of one product, the whole K loop.  Block index
+// wg = product * ublocks + u-block.
+template <int L, typename W>
+__device__ __forceinline__ void stream_block(const StreamParams& P, uint64_t wg, uint8_t* smem) {
   const uint64_t prod = wg / P.ublocks;
   const int U0 = 64 * (int)(wg - prod * P.ublocks);
   const uint32_t li = (uint32_t)(prod % P.lc);
@@ -364,6 +363,13 @@ void stream_kernel(const StreamParams P) {
     const int z = z0 + 8 * (rr >> 2) + 4 * g + (rr & 3);
     if (z < t) C[(size_t)u * t + z] = res[rr];
   }
+}
+
+template <int L, typename W, int WPE>
+__global__ __launch_bounds__(kStreamThreads) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
+void stream_kernel(const StreamParams P) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  stream_block<L, W>(P, blockIdx.x, smem);
 }
 
 }  // namespace pm

@@ -1,20 +1,27 @@
-// C-ABI of the GPU library: argument checks, launch geometry, dispatch.
+// C-ABI of the GPU library: argument checks, launch geometry, dispatch, plans.
+#include <algorithm>
+#include <atomic>
 #include <mutex>
 #include <new>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#include <vector>
 
 #include "../../include/polymul.h"
 #include "pm_common.h"
 #include "pm_mfma32.h"
 #include "pm_plain.h"
 #include "pm_stream.h"
+#include "pm_grouped.h"
 #include "pm_wide_host.h"
 
 using namespace pm;
 
 namespace {
+
+// Dynamic LDS limit per workgroup: the 160 KiB of a CU less room for static LDS.
+constexpr uint32_t kMaxLds = 160 * 1024 - 256;
 
 bool is_pow2(uint64_t x) { return x && !(x & (x - 1)); }
 int ilog2(uint64_t x) {
@@ -44,40 +51,24 @@ polymul_status check_arrays(const void* a, const void* b, const void* c, uint64_
   return POLYMUL_OK;
 }
 
+// POLYMUL_LOG=1 in the environment prints failing HIP calls to stderr.
+bool log_enabled() {
+  static const bool on = [] {
+    const char* v = getenv("POLYMUL_LOG");
+    return v && *v && *v != '0';
+  }();
+  return on;
+}
+
+polymul_status hip_fail(hipError_t e, const char* what) {
+  if (log_enabled()) fprintf(stderr, "polymul: %s failed: %s\n", what, hipGetErrorString(e));
+  return POLYMUL_EDEVICE;
+}
+
 polymul_status launch_status() {
   hipError_t e = hipGetLastError();
-  return e == hipSuccess ? POLYMUL_OK : POLYMUL_EDEVICE;
+  return e == hipSuccess ? POLYMUL_OK : hip_fail(e, "kernel launch");
 }
-
-// ----------------------------------------------------------- MFMA, 32-bit q
-struct Geometry32 {
-  uint32_t t, r, spd, rowlen, tz, tu, U, slots, a_plane, b_rows, b_rowstride, b_plane, E;
-};
-
-// Degree split n = t * r (Sec. 2.5): t is the Toeplitz tile side.
-Geometry32 geometry32(uint32_t n, int L) {
-  Geometry32 g{};
-  if (n <= 32) { g.t = n; g.r = 1; }
-  else if (n <= 1024) { g.t = 32; g.r = n / 32; }
-  else { g.t = 64; g.r = n / 64; }
-  g.spd = g.t >= 32 ? g.t / 32 : 1;
-  g.rowlen = 32 * g.spd;
-  g.tz = (g.t + 31) / 32;
-  g.tu = (g.r + 31) / 32;
-  g.U = g.tz * g.tu;
-  g.slots = g.U >= 4 ? 1 : 4 / g.U;
-  g.E = (g.r - 1) * g.t + 32 * g.tz - 1;
-  g.a_plane = (g.E + g.rowlen + 4 + 15) & ~15u;
-  uint32_t utiles = g.U >= 4 ? 4 / g.tz : g.tu;
-  if (utiles == 0) utiles = 1;
-  g.b_rows = 32 * utiles + g.r - 1;
-  g.b_rowstride = ((g.rowlen / 16) & 1) ? g.rowlen : g.rowlen + 16;
-  g.b_plane = (g.b_rows * g.b_rowstride + 15) & ~15u;
-  (void)L;
-  return g;
-}
-
-constexpr uint32_t kMaxLds = 160 * 1024;
 
 // Compute units of the current device (cached per device).
 uint32_t device_cus() {
@@ -97,53 +88,66 @@ uint32_t device_cus() {
   return cached;
 }
 
-template <int L, bool SMALL>
-polymul_status launch_mfma32_L(Mfma32Params& P, const Geometry32& g, hipStream_t s) {
-  static std::once_flag once;
-  static hipError_t attr_err = hipSuccess;
-  std::call_once(once, [] {
-    attr_err = hipFuncSetAttribute((const void*)mfma32_group_kernel<L, SMALL>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds);
-  });
-  if (attr_err != hipSuccess) return POLYMUL_EDEVICE;
-  P.slot_bytes = L * (g.a_plane + g.b_plane);
-  const uint32_t lds = P.slots * P.slot_bytes;
-  if (lds > kMaxLds) return POLYMUL_EUNSUPPORTED;
-  const uint64_t units = P.nprod << P.log2U;
-  const uint64_t groups = (units + 3) / 4;
-  // Persistent grid: as many workgroups as fit at once (LDS- and register-bound).
-  uint64_t blocks = groups;
-  if (blocks > 0x7FFFFFFFull) return POLYMUL_EUNSUPPORTED;
-  hipLaunchKernelGGL((mfma32_group_kernel<L, SMALL>), dim3((uint32_t)blocks), dim3(kThreads), lds, s, P);
-  return launch_status();
+// ------------------------------------------------------------- tile table
+// Toeplitz tile side t for the resident 32-bit path, per (log2 n, L); 0 = built-in choice.
+// Written by polymul_tune_set (the autotuner), read at every launch.
+std::atomic<uint32_t> g_tile[17][5];
+
+uint32_t default_tile(uint32_t n) {
+  if (n <= 32) return n;
+  if (n <= 1024) return 32;
+  return 64;
 }
 
-// nprod products (i -> global (i/lc)*nq_total + l0 + i%lc) with moduli qs[0..lc).
-template <typename W>
-polymul_status run_stream(const W* a, const W* b, W* c, uint32_t n, const uint64_t* qs, uint32_t lc,
-                          uint32_t nq_total, uint32_t l0, uint64_t nprod, hipStream_t s);
+uint32_t tile_for(uint32_t n, int L) {
+  const uint32_t t = g_tile[ilog2(n)][L].load(std::memory_order_relaxed);
+  return t ? t : default_tile(n);
+}
 
-polymul_status run_mfma32(const uint32_t* a, const uint32_t* b, uint32_t* c, uint32_t n, const uint32_t* qs,
-                          uint32_t lc, uint32_t nq_total, uint32_t l0, uint64_t nprod, hipStream_t s) {
-  if (n > 8192) {
-    // degree too large for both operands in LDS: K-streaming kernel, moduli in chunks of kMaxQS
-    uint64_t q64[kMaxQ];
-    for (uint32_t i = 0; i < lc; ++i) q64[i] = qs[i];
-    if (lc <= (uint32_t)kMaxQS) return run_stream<uint32_t>(a, b, c, n, q64, lc, nq_total, l0, nprod, s);
-    // split the channel range (nprod = batch * lc)
-    const uint64_t batch = nprod / lc;
-    for (uint32_t c0 = 0; c0 < lc; c0 += kMaxQS) {
-      const uint32_t cc = lc - c0 < (uint32_t)kMaxQS ? lc - c0 : (uint32_t)kMaxQS;
-      polymul_status st = run_stream<uint32_t>(a, b, c, n, q64 + c0, cc, nq_total, l0 + c0, batch * cc, s);
-      if (st != POLYMUL_OK) return st;
-    }
-    return POLYMUL_OK;
-  }
-  int L = 1;
-  for (uint32_t i = 0; i < lc; ++i) L = L > limbs_for_q32(qs[i]) ? L : limbs_for_q32(qs[i]);
-  if (L < 2) L = 2;
-  Geometry32 g = geometry32(n, L);
-  Mfma32Params P{};
+// Valid tile sides for the resident path: n itself when n <= 32, else a power of two in [32, min(n, 128)].
+bool tile_ok(uint32_t n, uint32_t t) {
+  if (n <= 32) return t == n;
+  return is_pow2(t) && t >= 32 && t <= 128 && t <= n;
+}
+
+// ----------------------------------------------------------- MFMA, 32-bit q
+struct Geometry32 {
+  uint32_t t, r, spd, rowlen, tz, tu, U, slots, a_plane, b_rows, b_rowstride, b_plane, E;
+};
+
+// Degree split n = t * r (Sec. 2.5): t is the Toeplitz tile side.
+Geometry32 geometry32(uint32_t n, uint32_t t) {
+  Geometry32 g{};
+  g.t = t;
+  g.r = n / t;
+  g.spd = g.t >= 32 ? g.t / 32 : 1;
+  g.rowlen = 32 * g.spd;
+  g.tz = (g.t + 31) / 32;
+  g.tu = (g.r + 31) / 32;
+  g.U = g.tz * g.tu;
+  g.slots = g.U >= 4 ? 1 : 4 / g.U;
+  g.E = (g.r - 1) * g.t + 32 * g.tz - 1;
+  g.a_plane = (g.E + g.rowlen + 4 + 15) & ~15u;
+  uint32_t utiles = g.U >= 4 ? (4 / g.tz ? 4 / g.tz : 1) : g.tu;
+  g.b_rows = 32 * utiles + g.r - 1;
+  g.b_rowstride = ((g.rowlen / 16) & 1) ? g.rowlen : g.rowlen + 16;
+  g.b_plane = (g.b_rows * g.b_rowstride + 15) & ~15u;
+  return g;
+}
+
+int limbs32(const uint32_t* qs, uint32_t lc) {
+  int L = 2;
+  for (uint32_t i = 0; i < lc; ++i) L = std::max(L, limbs_for_q32(qs[i]));
+  return L;
+}
+
+// Resident-kernel parameters; *lds gets the dynamic LDS bytes per workgroup.
+polymul_status fill_mfma32(Mfma32Params& P, const uint32_t* a, const uint32_t* b, uint32_t* c, uint32_t n,
+                           const uint32_t* qs, uint32_t lc, uint32_t nq_total, uint32_t l0, uint64_t nprod, int L,
+                           uint32_t t, uint32_t* lds) {
+  if (!tile_ok(n, t)) return POLYMUL_EINVAL;
+  const Geometry32 g = geometry32(n, t);
+  P = Mfma32Params{};
   P.a = a; P.b = b; P.c = c;
   P.nprod = nprod;
   P.n = n; P.t = g.t; P.r = g.r;
@@ -156,6 +160,7 @@ polymul_status run_mfma32(const uint32_t* a, const uint32_t* b, uint32_t* c, uin
   P.a_plane = g.a_plane; P.b_rows = g.b_rows; P.b_rowstride = g.b_rowstride; P.b_plane = g.b_plane;
   P.E = g.E;
   P.lc = lc; P.nq_total = nq_total; P.l0 = l0;
+  P.slot_bytes = (uint32_t)L * (g.a_plane + g.b_plane);
   // Epilogue choice: the one-reduction form needs sum_s P_s * n * 2^14 * |rcent_s| < 2^62,
   // P_s = number of limb pairs (i, j) with i + j = s.
   bool fast = true;
@@ -164,51 +169,52 @@ polymul_status run_mfma32(const uint32_t* a, const uint32_t* b, uint32_t* c, uin
     unsigned __int128 bound = 0;
     uint64_t pw = 1 % qs[i];
     for (int s = 0; s < 2 * L - 1; ++s) {
-      int64_t c = (int64_t)pw;
-      if (pw > qs[i] / 2) c -= (int64_t)qs[i];
-      P.rcent[i][s] = (int32_t)c;
-      uint64_t pairs = (uint64_t)((s < L ? s : 2 * L - 2 - s) + 1);
-      bound += (unsigned __int128)pairs * n * 16384u * (uint64_t)(c < 0 ? -c : c);
+      int64_t cc = (int64_t)pw;
+      if (pw > qs[i] / 2) cc -= (int64_t)qs[i];
+      P.rcent[i][s] = (int32_t)cc;
+      const uint64_t pairs = (uint64_t)((s < L ? s : 2 * L - 2 - s) + 1);
+      bound += (unsigned __int128)pairs * n * 16384u * (uint64_t)(cc < 0 ? -cc : cc);
       pw = (pw * 256) % qs[i];
     }
     if (bound >= ((unsigned __int128)1 << 62)) fast = false;
   }
   P.fast_epilogue = fast ? 1u : 0u;
-  const bool small = n < 4;
-  switch (L) {
-    case 2: return small ? launch_mfma32_L<2, true>(P, g, s) : launch_mfma32_L<2, false>(P, g, s);
-    case 3: return small ? launch_mfma32_L<3, true>(P, g, s) : launch_mfma32_L<3, false>(P, g, s);
-    default: return small ? launch_mfma32_L<4, true>(P, g, s) : launch_mfma32_L<4, false>(P, g, s);
-  }
+  *lds = P.slots * P.slot_bytes;
+  return *lds <= kMaxLds ? POLYMUL_OK : POLYMUL_EUNSUPPORTED;
 }
 
-// ------------------------------------------------------- streaming kernel
-template <int L, typename W, int WPE>
-polymul_status launch_stream_L(const StreamParams& P, uint32_t lds, uint64_t blocks, hipStream_t s) {
+// Allow up to kMaxLds of dynamic LDS for kernel K (once per process).  Called
+// outside stream capture: plans set their kernels' attributes before capturing.
+template <const void* (*K)()>
+polymul_status allow_lds() {
   static std::once_flag once;
-  static hipError_t attr_err = hipSuccess;
-  std::call_once(once, [] {
-    attr_err = hipFuncSetAttribute((const void*)stream_kernel<L, W, WPE>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds);
-  });
-  if (attr_err != hipSuccess) return POLYMUL_EDEVICE;
-  hipLaunchKernelGGL((stream_kernel<L, W, WPE>), dim3((uint32_t)blocks), dim3(kStreamThreads), lds, s, P);
+  static hipError_t err = hipSuccess;
+  std::call_once(once, [] { err = hipFuncSetAttribute(K(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds); });
+  return err == hipSuccess ? POLYMUL_OK : hip_fail(err, "hipFuncSetAttribute");
+}
+template <int L, bool SMALL> const void* k_group() { return (const void*)mfma32_group_kernel<L, SMALL>; }
+template <int L, typename W, int WPE> const void* k_stream() { return (const void*)stream_kernel<L, W, WPE>; }
+const void* k_grouped() { return (const void*)grouped_kernel<4>; }
+
+template <int L, bool SMALL>
+polymul_status launch_mfma32_L(const Mfma32Params& P, uint32_t lds, hipStream_t s) {
+  if (allow_lds<k_group<L, SMALL>>() != POLYMUL_OK) return POLYMUL_EDEVICE;
+  const uint64_t groups = ((P.nprod << P.log2U) + 3) / 4;
+  if (groups > 0x7FFFFFFFull) return POLYMUL_EUNSUPPORTED;
+  hipLaunchKernelGGL((mfma32_group_kernel<L, SMALL>), dim3((uint32_t)groups), dim3(kThreads), lds, s, P);
   return launch_status();
 }
 
-// nprod products of degree bound n (i -> global (i/lc)*nq_total + l0 + i%lc), moduli qs[0..lc).
-template <typename W>
-polymul_status run_stream(const W* a, const W* b, W* c, uint32_t n, const uint64_t* qs, uint32_t lc,
-                          uint32_t nq_total, uint32_t l0, uint64_t nprod, hipStream_t s) {
-  int L = 1;
-  for (uint32_t i = 0; i < lc; ++i) {
-    const int li = limbs_for_q64(qs[i]);
-    L = L > li ? L : li;
-  }
-  if (L < 2) L = 2;
-  if (sizeof(W) == 4 && L > 4) return POLYMUL_EINVAL;
-  L = L <= 4 ? 4 : 8;  // two instantiations: up to 4 and up to 8 limbs
-  StreamParams P{};
+// --------------------------------------------------------- streaming kernel
+int limbs64(const uint64_t* qs, uint32_t lc) {
+  int L = 2;
+  for (uint32_t i = 0; i < lc; ++i) L = std::max(L, limbs_for_q64(qs[i]));
+  return L <= 4 ? 4 : 8;  // two instantiations: up to 4 and up to 8 limbs
+}
+
+polymul_status fill_stream(StreamParams& P, const void* a, const void* b, void* c, uint32_t n, const uint64_t* qs,
+                           uint32_t lc, uint32_t nq_total, uint32_t l0, uint64_t nprod, int L, uint32_t* lds) {
+  P = StreamParams{};
   P.a = a; P.b = b; P.c = c;
   P.nprod = nprod;
   P.n = n;
@@ -224,18 +230,131 @@ polymul_status run_stream(const W* a, const W* b, W* c, uint32_t n, const uint64
   P.dc = P.r < 16 ? P.r : 16;
   P.nchunks = P.r / P.dc;
   const uint32_t kflush = L <= 4 ? 16384u : 8192u;  // K values per exact int32 class sum
-  uint32_t fe = kflush / (P.dc * P.t);
+  const uint32_t fe = kflush / (P.dc * P.t);
   P.flush_every = fe < 1 ? 1 : fe;
   P.a_win = ((P.dc - 1) * P.t + 32 * P.tz + P.rowlen + 4 + 15) & ~15u;
   P.lds_b = 2u * (uint32_t)L * P.a_win;
-  const uint32_t lds = P.lds_b + (uint32_t)L * kRing * P.rs;
-  if (lds > kMaxLds) return POLYMUL_EUNSUPPORTED;
   P.lc = lc; P.nq_total = nq_total; P.l0 = l0;
   for (uint32_t i = 0; i < lc; ++i) P.mods[i] = make_mod64(qs[i], L);
-  const uint64_t blocks = nprod * P.ublocks;
+  *lds = P.lds_b + (uint32_t)L * kRing * P.rs;
+  return *lds <= kMaxLds ? POLYMUL_OK : POLYMUL_EUNSUPPORTED;
+}
+
+template <int L, typename W, int WPE>
+polymul_status launch_stream_L(const StreamParams& P, uint32_t lds, hipStream_t s) {
+  if (allow_lds<k_stream<L, W, WPE>>() != POLYMUL_OK) return POLYMUL_EDEVICE;
+  const uint64_t blocks = P.nprod * P.ublocks;
   if (blocks > 0x7FFFFFFFull) return POLYMUL_EUNSUPPORTED;
-  if (L == 4) return launch_stream_L<4, W, 2>(P, lds, blocks, s);
-  return launch_stream_L<8, W, 1>(P, lds, blocks, s);
+  hipLaunchKernelGGL((stream_kernel<L, W, WPE>), dim3((uint32_t)blocks), dim3(kStreamThreads), lds, s, P);
+  return launch_status();
+}
+
+// nprod products of degree bound n (i -> global (i/lc)*nq_total + l0 + i%lc), moduli qs[0..lc <= kMaxQS).
+template <typename W>
+polymul_status run_stream(const W* a, const W* b, W* c, uint32_t n, const uint64_t* qs, uint32_t lc,
+                          uint32_t nq_total, uint32_t l0, uint64_t nprod, hipStream_t s) {
+  const int L = limbs64(qs, lc);
+  if (sizeof(W) == 4 && L > 4) return POLYMUL_EINVAL;
+  StreamParams P;
+  uint32_t lds;
+  polymul_status st = fill_stream(P, a, b, c, n, qs, lc, nq_total, l0, nprod, L, &lds);
+  if (st != POLYMUL_OK) return st;
+  if (L == 4) return launch_stream_L<4, W, 2>(P, lds, s);
+  return launch_stream_L<8, W, 1>(P, lds, s);
+}
+
+// nprod products (i -> global (i/lc)*nq_total + l0 + i%lc) with moduli qs[0..lc <= kMaxQ).
+polymul_status run_mfma32(const uint32_t* a, const uint32_t* b, uint32_t* c, uint32_t n, const uint32_t* qs,
+                          uint32_t lc, uint32_t nq_total, uint32_t l0, uint64_t nprod, hipStream_t s) {
+  if (n > 8192) {
+    // degree too large for both operands in LDS: K-streaming kernel, moduli in chunks of kMaxQS
+    uint64_t q64[kMaxQ];
+    for (uint32_t i = 0; i < lc; ++i) q64[i] = qs[i];
+    const uint64_t batch = nprod / lc;
+    for (uint32_t c0 = 0; c0 < lc; c0 += kMaxQS) {
+      const uint32_t cc = std::min(lc - c0, (uint32_t)kMaxQS);
+      const uint64_t np = cc == lc ? nprod : batch * cc;
+      polymul_status st = run_stream<uint32_t>(a, b, c, n, q64 + c0, cc, nq_total, l0 + c0, np, s);
+      if (st != POLYMUL_OK) return st;
+    }
+    return POLYMUL_OK;
+  }
+  const int L = limbs32(qs, lc);
+  Mfma32Params P;
+  uint32_t lds;
+  polymul_status st = fill_mfma32(P, a, b, c, n, qs, lc, nq_total, l0, nprod, L, tile_for(n, L), &lds);
+  if (st != POLYMUL_OK) return st;
+  const bool small = n < 4;
+  switch (L) {
+    case 2: return small ? launch_mfma32_L<2, true>(P, lds, s) : launch_mfma32_L<2, false>(P, lds, s);
+    case 3: return small ? launch_mfma32_L<3, true>(P, lds, s) : launch_mfma32_L<3, false>(P, lds, s);
+    default: return small ? launch_mfma32_L<4, true>(P, lds, s) : launch_mfma32_L<4, false>(P, lds, s);
+  }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------- plans
+struct polymul_plan {
+  GroupJob* d_jobs = nullptr;       // device job table
+  WorkItem* d_items = nullptr;      // device work list (largest first)
+  uint32_t* d_counter = nullptr;    // queue counter
+  uint32_t nitems = 0;
+  uint32_t lds = 0;                 // dynamic LDS of the grouped launch
+  uint32_t grid = 0;
+  // 64-bit groups run as separate streaming launches after the grouped one
+  std::vector<StreamParams> wide;
+  std::vector<uint32_t> wide_lds;
+  std::vector<int> wide_L;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool use_graph = true;
+};
+
+namespace {
+
+polymul_status plan_attrs() {
+  if (allow_lds<k_grouped>() != POLYMUL_OK) return POLYMUL_EDEVICE;
+  if (allow_lds<k_stream<4, uint64_t, 2>>() != POLYMUL_OK) return POLYMUL_EDEVICE;
+  if (allow_lds<k_stream<8, uint64_t, 1>>() != POLYMUL_OK) return POLYMUL_EDEVICE;
+  return POLYMUL_OK;
+}
+
+polymul_status plan_launch(const polymul_plan* p, hipStream_t s) {
+  if (p->nitems) {
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, p->d_counter);
+    hipLaunchKernelGGL(grouped_kernel<4>, dim3(p->grid), dim3(kThreads), p->lds, s, p->d_jobs, p->d_items,
+                       p->nitems, p->d_counter);
+    polymul_status st = launch_status();
+    if (st != POLYMUL_OK) return st;
+  }
+  for (size_t i = 0; i < p->wide.size(); ++i) {
+    polymul_status st = p->wide_L[i] == 4 ? launch_stream_L<4, uint64_t, 2>(p->wide[i], p->wide_lds[i], s)
+                                          : launch_stream_L<8, uint64_t, 1>(p->wide[i], p->wide_lds[i], s);
+    if (st != POLYMUL_OK) return st;
+  }
+  return POLYMUL_OK;
+}
+
+void plan_free(polymul_plan* p) {
+  if (!p) return;
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  if (p->d_jobs) (void)hipFree(p->d_jobs);
+  if (p->d_items) (void)hipFree(p->d_items);
+  if (p->d_counter) (void)hipFree(p->d_counter);
+  delete p;
+}
+
+// MFMA work of one item, for the largest-first order.
+uint64_t item_cost(const GroupJob& j) {
+  if (j.kind == kJobResident) {
+    const uint64_t steps = (uint64_t)j.rp.r << j.rp.log2spd;
+    return 4 * steps;  // four tiles
+  }
+  return (uint64_t)4 * ((uint64_t)j.sp.r << j.sp.log2spd);
 }
 
 }  // namespace
@@ -272,7 +391,7 @@ polymul_status polymul_negacyclic_rns(const uint32_t* a, const uint32_t* b, uint
   polymul_status st = check_arrays(a, b, c, n, batch, L, 4, &bytes);
   if (st != POLYMUL_OK || batch == 0) return st;
   for (uint32_t l0 = 0; l0 < L; l0 += kMaxQ) {
-    uint32_t lc = L - l0 < (uint32_t)kMaxQ ? L - l0 : (uint32_t)kMaxQ;
+    const uint32_t lc = std::min(L - l0, (uint32_t)kMaxQ);
     st = run_mfma32(a, b, c, (uint32_t)n, q + l0, lc, L, l0, batch * lc, stream);
     if (st != POLYMUL_OK) return st;
   }
@@ -289,7 +408,7 @@ polymul_status polymul_negacyclic_plain(const uint32_t* a, const uint32_t* b, ui
   P.a = a; P.b = b; P.c = c; P.batch = batch; P.n = (uint32_t)n;
   P.blocks_per_prod = (uint32_t)((n + kPlainOut - 1) / kPlainOut);
   P.m = make_mod32(q, 4);
-  uint64_t blocks = batch * P.blocks_per_prod;
+  const uint64_t blocks = batch * P.blocks_per_prod;
   if (blocks > 0x7FFFFFFFull) return POLYMUL_EUNSUPPORTED;
   hipLaunchKernelGGL(plain_kernel, dim3((uint32_t)blocks), dim3(kPlainThreads), 0, stream, P);
   return launch_status();
@@ -304,23 +423,134 @@ polymul_status polymul_negacyclic_u64(const uint64_t* a, const uint64_t* b, uint
   return run_stream<uint64_t>(a, b, c, (uint32_t)n, &q, 1, 1, 0, batch, stream);
 }
 
-struct polymul_plan {
-  int unused;
-};
-
 polymul_status polymul_plan_create(polymul_plan** plan, const polymul_group* groups, uint32_t ngroups,
                                    uint32_t flags) {
-  (void)groups; (void)ngroups; (void)flags;
   if (!plan) return POLYMUL_EINVAL;
   *plan = nullptr;
-  return POLYMUL_EUNSUPPORTED;
+  if (ngroups && !groups) return POLYMUL_EINVAL;
+  if (flags & ~POLYMUL_PLAN_NO_GRAPH) return POLYMUL_EINVAL;
+  // ---- validate every group before any HIP call (GenConfig / ExtractDimensions)
+  for (uint32_t g = 0; g < ngroups; ++g) {
+    const polymul_group& G = groups[g];
+    if (G.elem_bytes != 4 && G.elem_bytes != 8) return POLYMUL_EINVAL;
+    if (G.q < 2 || (G.elem_bytes == 4 && G.q > 0xFFFFFFFFull)) return POLYMUL_EINVAL;
+    uint64_t bytes;
+    polymul_status st = check_arrays(G.a, G.b, G.c, G.n, G.count, 1, G.elem_bytes, &bytes);
+    if (st != POLYMUL_OK) return st;
+  }
+  polymul_plan* p = new (std::nothrow) polymul_plan();
+  if (!p) return POLYMUL_ENOMEM;
+  p->use_graph = !(flags & POLYMUL_PLAN_NO_GRAPH);
+  std::vector<GroupJob> jobs;
+  std::vector<WorkItem> items;
+  for (uint32_t g = 0; g < ngroups; ++g) {
+    const polymul_group& G = groups[g];
+    if (G.count == 0) continue;
+    const uint32_t n = (uint32_t)G.n;
+    if (G.elem_bytes == 8) {
+      StreamParams sp;
+      uint32_t lds;
+      const int L = limbs64(&G.q, 1);
+      polymul_status st = fill_stream(sp, G.a, G.b, G.c, n, &G.q, 1, 1, 0, G.count, L, &lds);
+      if (st != POLYMUL_OK) { plan_free(p); return st; }
+      p->wide.push_back(sp);
+      p->wide_lds.push_back(lds);
+      p->wide_L.push_back(L);
+      continue;
+    }
+    GroupJob job{};
+    const uint32_t q32 = (uint32_t)G.q;
+    uint32_t lds = 0;
+    polymul_status st;
+    if (n >= 4 && n <= 4096) {
+      job.kind = kJobResident;
+      st = fill_mfma32(job.rp, (const uint32_t*)G.a, (const uint32_t*)G.b, (uint32_t*)G.c, n, &q32, 1, 1, 0,
+                       G.count, 4, tile_for(n, 4), &lds);
+    } else {
+      job.kind = kJobStream;
+      const uint64_t q64 = G.q;
+      st = fill_stream(job.sp, G.a, G.b, G.c, n, &q64, 1, 1, 0, G.count, 4, &lds);
+    }
+    if (st != POLYMUL_OK) { plan_free(p); return st; }
+    p->lds = std::max(p->lds, lds);
+    const uint32_t jid = (uint32_t)jobs.size();
+    const uint64_t cnt = job.kind == kJobResident ? ((G.count << job.rp.log2U) + 3) / 4 : G.count * job.sp.ublocks;
+    if (cnt + items.size() > 0xFFFFFFFFull) { plan_free(p); return POLYMUL_EUNSUPPORTED; }
+    for (uint64_t i = 0; i < cnt; ++i) items.push_back(WorkItem{jid, (uint32_t)i});
+    jobs.push_back(job);
+  }
+  // largest items first
+  std::stable_sort(items.begin(), items.end(), [&](const WorkItem& x, const WorkItem& y) {
+    return item_cost(jobs[x.group]) > item_cost(jobs[y.group]);
+  });
+  p->nitems = (uint32_t)items.size();
+  if (p->nitems) {
+    if (hipMalloc((void**)&p->d_jobs, jobs.size() * sizeof(GroupJob)) != hipSuccess ||
+        hipMalloc((void**)&p->d_items, items.size() * sizeof(WorkItem)) != hipSuccess ||
+        hipMalloc((void**)&p->d_counter, 256) != hipSuccess) {
+      plan_free(p);
+      return POLYMUL_ENOMEM;
+    }
+    hipError_t e = hipMemcpy(p->d_jobs, jobs.data(), jobs.size() * sizeof(GroupJob), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->d_items, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice);
+    if (e != hipSuccess) { plan_free(p); return hip_fail(e, "hipMemcpy (plan tables)"); }
+    // persistent grid: as many workgroups as fit at once (two per CU within the register budget)
+    const uint32_t per_cu = std::max(1u, std::min(2u, kMaxLds / std::max(p->lds, 1u)));
+    p->grid = std::min<uint64_t>(p->nitems, (uint64_t)device_cus() * per_cu);
+  }
+  if (plan_attrs() != POLYMUL_OK) {
+    plan_free(p);
+    return POLYMUL_EDEVICE;
+  }
+  if (p->use_graph && (p->nitems || !p->wide.empty())) {
+    hipError_t e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) { plan_free(p); return hip_fail(e, "hipStreamCreateWithFlags"); }
+    e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) { plan_free(p); return hip_fail(e, "hipStreamBeginCapture"); }
+    const polymul_status st = plan_launch(p, p->cap_stream);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(p->cap_stream, &graph);
+    p->graph = graph;
+    if (st != POLYMUL_OK || e != hipSuccess || !graph) {
+      plan_free(p);
+      return e != hipSuccess ? hip_fail(e, "hipStreamEndCapture") : POLYMUL_EDEVICE;
+    }
+    e = hipGraphInstantiate(&p->exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) { plan_free(p); return hip_fail(e, "hipGraphInstantiate"); }
+  }
+  *plan = p;
+  return POLYMUL_OK;
 }
+
 polymul_status polymul_plan_execute(polymul_plan* plan, hipStream_t stream) {
-  (void)stream;
-  return plan ? POLYMUL_EUNSUPPORTED : POLYMUL_EINVAL;
+  if (!plan) return POLYMUL_EINVAL;
+  if (plan->exec) {
+    const hipError_t e = hipGraphLaunch(plan->exec, stream);
+    return e == hipSuccess ? POLYMUL_OK : hip_fail(e, "hipGraphLaunch");
+  }
+  return plan_launch(plan, stream);
 }
+
 polymul_status polymul_plan_destroy(polymul_plan* plan) {
-  delete plan;
+  plan_free(plan);
+  return POLYMUL_OK;
+}
+
+polymul_status polymul_tune_set(uint64_t n, uint32_t L, uint32_t t) {
+  if (!is_pow2(n) || n > 65536 || L < 1 || L > 4) return POLYMUL_EINVAL;
+  if (t != 0 && !tile_ok((uint32_t)n, t)) return POLYMUL_EINVAL;
+  if (t != 0) {
+    // the geometry must fit in LDS at the largest slot count
+    const Geometry32 g = geometry32((uint32_t)n, t);
+    if ((uint64_t)g.slots * (uint32_t)L * (g.a_plane + g.b_plane) > kMaxLds) return POLYMUL_EUNSUPPORTED;
+  }
+  g_tile[ilog2(n)][L].store(t, std::memory_order_relaxed);
+  return POLYMUL_OK;
+}
+
+polymul_status polymul_tune_get(uint64_t n, uint32_t L, uint32_t* t) {
+  if (!is_pow2(n) || n > 65536 || L < 1 || L > 4 || !t) return POLYMUL_EINVAL;
+  *t = tile_for((uint32_t)n, (int)L);
   return POLYMUL_OK;
 }
 

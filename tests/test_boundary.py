@@ -44,6 +44,7 @@ def test_status_strings():
 
 # Fake, never-dereferenced device addresses: argument errors must be reported first.
 A, B, C = 0x10000000, 0x20000000, 0x30000000
+C_ = C
 
 
 def call(name, *args):
@@ -110,6 +111,33 @@ def test_plan_arguments():
     assert call("polymul_plan_create", None, None, 0, 0) == EINVAL
     assert call("polymul_plan_execute", None, None) == EINVAL
     assert call("polymul_plan_destroy", None) == 0
+
+
+def test_plan_group_validation():
+    import ctypes as C
+    from paper_2307_06554_amd.binding import _Group
+    h = C.c_void_p()
+    good = _Group(A, B, C_, 256, 17, 2, 4)
+    for bad in (_Group(A, B, C_, 255, 17, 2, 4), _Group(A, B, C_, 256, 1, 2, 4), _Group(A, B, C_, 256, 17, 2, 3),
+                _Group(A, B, C_, 256, 1 << 33, 2, 4), _Group(0, B, C_, 256, 17, 2, 4), _Group(A + 4, B, C_, 256, 17, 2, 4)):
+        arr = (_Group * 2)(good, bad)
+        assert call("polymul_plan_create", C.byref(h), C.cast(arr, C.c_void_p), 2, 0) == EINVAL
+    arr = (_Group * 1)(_Group(A, B, A, 256, 17, 2, 4))
+    assert call("polymul_plan_create", C.byref(h), C.cast(arr, C.c_void_p), 1, 0) == EALIAS
+    arr = (_Group * 1)(good)
+    assert call("polymul_plan_create", C.byref(h), C.cast(arr, C.c_void_p), 1, 0x80) == EINVAL
+    assert h.value is None
+
+
+def test_tile_table():
+    for n, t in ((4096, 64), (4096, 128), (4096, 32), (1024, 64), (16, 16)):
+        pm.polymul_tune_set(n, 4, t)
+        assert pm.polymul_tune_get(n, 4) == t
+        pm.polymul_tune_set(n, 4, 0)
+    assert pm.polymul_tune_get(4096, 4) == 64 and pm.polymul_tune_get(256, 2) == 32
+    for n, L, t in ((4096, 4, 48), (4096, 4, 256), (4096, 5, 64), (1000, 4, 32), (16, 4, 32), (64, 4, 128)):
+        with pytest.raises(pm.PolymulError):
+            pm.polymul_tune_set(n, L, t)
 
 
 def test_binding_refuses_host_tensors():

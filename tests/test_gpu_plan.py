@@ -1,0 +1,97 @@
+"""GPU: grouped persistent plans (uneven degrees and moduli in one launch,
+replayed from a HIP graph) and the tile table of the resident path."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2307_06554_amd as pm
+from paper_2307_06554_amd import inputs
+from gpu_util import to_dev, to_host, mismatch_report
+
+pytestmark = pytest.mark.gpu
+
+
+def _groups_from_workload(w):
+    out = []
+    for g in w.groups:
+        a, b = to_dev(g.a), to_dev(g.b)
+        out.append((a, b, torch.zeros_like(a), g.n, g.q, g))
+    return out
+
+
+@pytest.mark.parametrize("flags", [0, pm.binding.POLYMUL_PLAN_NO_GRAPH])
+def test_plan_workload3(flags):
+    """The uneven workload (2048x256, 512x1024, 128x2048, 64x4096, 16x8192, one
+    30-bit prime per group) in one plan; every replay checked, with eager work
+    (zeroing the outputs, an unrelated product) between replays."""
+    w = inputs.make_workload(3)
+    gs = _groups_from_workload(w)
+    want = [oracle.negacyclic(g.a, g.b, g.q) for (_, _, _, _, _, g) in gs]
+    plan = pm.Plan([(a, b, c, n, q) for (a, b, c, n, q, _) in gs], flags)
+    rng = np.random.Generator(np.random.PCG64(9))
+    xa = to_dev(rng.integers(0, 3329, size=(4, 256), dtype=np.uint64).astype(np.uint32))
+    for rep in range(3):
+        for (_, _, c, _, _, _) in gs:
+            c.zero_()
+        pm.polymul_negacyclic(xa, xa, 3329)  # eager work between replays
+        torch.cuda.synchronize()
+        plan.execute()
+        torch.cuda.synchronize()
+        for (_, _, c, _, _, g), wv in zip(gs, want):
+            got = to_host(c, np.uint32)
+            assert np.array_equal(got, wv), f"replay {rep}, n={g.n}: " + mismatch_report(got, wv)
+    plan.close()
+
+
+def test_plan_mixed_degrees_and_word_sizes():
+    rng = np.random.Generator(np.random.PCG64(17))
+    specs = [(1, 17, 4, 5), (2, 3329, 4, 3), (8, 65537, 4, 7), (64, 1068236801, 4, 9), (256, (1 << 32) - 5, 4, 6),
+             (4096, 1068236801, 4, 2), (8192, 3329, 4, 1), (16384, 1068236801, 4, 1),
+             (64, inputs.GOLDILOCKS, 8, 3), (1024, (1 << 64) - 59, 8, 2), (16, 1 << 40, 8, 2)]
+    groups, refs = [], []
+    for n, q, eb, count in specs:
+        dt = np.uint32 if eb == 4 else np.uint64
+        a = rng.integers(0, q, size=(count, n), dtype=np.uint64).astype(dt)
+        b = rng.integers(0, q, size=(count, n), dtype=np.uint64).astype(dt)
+        da, db = to_dev(a), to_dev(b)
+        groups.append((da, db, torch.zeros_like(da), n, q))
+        refs.append((a, b, q, dt))
+    plan = pm.Plan(groups)
+    for rep in range(2):
+        for g in groups:
+            g[2].zero_()
+        plan.execute()
+        torch.cuda.synchronize()
+        for (da, db, dc, n, q), (a, b, q2, dt) in zip(groups, refs):
+            got = to_host(dc, dt)
+            wv = oracle.negacyclic(a, b, q)
+            assert np.array_equal(got, wv), f"replay {rep}, n={n}, q={q}: " + mismatch_report(got, wv)
+    plan.close()
+
+
+def test_plan_empty_groups():
+    a = torch.zeros((0, 256), dtype=torch.int32, device="cuda")
+    plan = pm.Plan([(a, a.clone(), a.clone(), 256, 17)])
+    plan.execute()
+    torch.cuda.synchronize()
+    plan.close()
+    plan = pm.Plan([])
+    plan.execute()
+    plan.close()
+
+
+@pytest.mark.parametrize("n,t", [(256, 64), (256, 128), (1024, 64), (1024, 128), (2048, 32), (2048, 128),
+                                 (4096, 32), (4096, 128), (8192, 32), (8192, 128), (128, 128)])
+def test_tile_table_parity(n, t):
+    q = 1068236801
+    rng = np.random.Generator(np.random.PCG64(n * t))
+    a = rng.integers(0, q, size=(5, n), dtype=np.uint64).astype(np.uint32)
+    b = rng.integers(0, q, size=(5, n), dtype=np.uint64).astype(np.uint32)
+    try:
+        pm.polymul_tune_set(n, 4, t)
+        got = to_host(pm.polymul_negacyclic(to_dev(a), to_dev(b), q), np.uint32)
+    finally:
+        pm.polymul_tune_set(n, 4, 0)
+    wv = oracle.negacyclic(a, b, q)
+    assert np.array_equal(got, wv), mismatch_report(got, wv)
