@@ -4,7 +4,8 @@
 One step = one pass of the whole path over one batch: the n = 4096 RNS workload
 (256 ciphertext-like pairs x 8 residue channels with distinct 30-bit primes
 q_i = 1 mod 2n, i.e. 2048 independent limb-products) through
-polymul_negacyclic_rns, inputs already resident in HBM.  Prints one JSON line.
+polymul_negacyclic_rns, inputs already resident in HBM.  Prints one JSON line
+on stdout.  --all also times the other workloads (to stderr).
 """
 import argparse
 import hashlib
@@ -18,8 +19,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "negacyclic polymuls/sec at n=4096 30-bit q (int8-MFMA vs plain int); % int8 peak"
 PEAK_INT8_TOPS = 5000.0      # MI355X dense int8 MFMA, published
-PEAK_HBM_GBS = 8000.0
 WORKLOAD_INDEX = 2
+KERNEL = "mfma32_group_kernel<4,false>"
 
 
 def csrc_hash():
@@ -31,10 +32,10 @@ def csrc_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel_name):
-    """HBM bytes per launch from the committed rocprofv3 --pmc summary, only if it
-    was taken on the current kernel sources."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel_name}.json")
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    --pmc summary, only if it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic_mfma32_group_kernel_n4096_rns8.json")
     try:
         with open(path) as f:
             rec = json.load(f)
@@ -42,11 +43,13 @@ def measured_traffic(kernel_name):
         return None
     if rec.get("csrc_hash") != csrc_hash():
         return None
-    return rec.get("bytes_per_launch")
+    return rec.get("hbm_bytes_per_launch")
 
 
-def time_steps(fn, steps, warmup, stream):
+def time_steps(fn, steps, warmup):
+    """Average milliseconds per step, events on the launch stream (torch's current)."""
     import torch
+    stream = torch.cuda.current_stream()
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
@@ -64,19 +67,56 @@ def cpu_baseline(w, budget_s):
     """The oracle, as it is, on a bounded sample of the same workload."""
     import numpy as np
     import oracle
-    q = w.qs[0]
-    a, b = w.a[:, 0], w.b[:, 0]
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    # calibrate on one product, then size the sample to about budget_s seconds
+    B, L, n = w.a.shape
+    cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
     t0 = time.perf_counter()
-    oracle.negacyclic(a[:1], b[:1], q)
-    one = time.perf_counter() - t0
-    count = int(max(1, min(a.shape[0], budget_s / max(one, 1e-6) * min(cores, 8))))
+    oracle.negacyclic_rns(w.a[:1], w.b[:1], w.qs)  # one pair = L products, also the calibration
+    per_pair = time.perf_counter() - t0
+    pairs = int(max(1, min(B, budget_s / max(per_pair, 1e-6))))
     t0 = time.perf_counter()
-    oracle.negacyclic(a[:count], b[:count], q)
+    oracle.negacyclic_rns(w.a[:pairs], w.b[:pairs], w.qs)
     dt = time.perf_counter() - t0
-    return {"value": count / dt, "unit": "polymuls/s", "cores": cores, "kind": "oracle",
-            "sample": f"{count} products of channel 0 (n=4096, q={q}), {dt:.1f} s wall"}
+    return {"value": pairs * L / dt, "unit": "polymuls/s", "cores": cores, "kind": "oracle",
+            "sample": f"{pairs} of {B} ciphertext pairs x {L} channels (n={n}, 30-bit q), {dt:.1f} s wall"}
+
+
+def other_workloads(steps, warmup):
+    """The remaining workloads, each timed the same way; printed to stderr."""
+    import numpy as np
+    import torch
+    import paper_2307_06554_amd as pm
+    from paper_2307_06554_amd import inputs
+    dev = torch.device("cuda:0")
+    out = {}
+    for idx in (0, 1):
+        w = inputs.make_workload(idx)
+        a = torch.from_numpy(w.a.view(np.int32)).to(dev)
+        b = torch.from_numpy(w.b.view(np.int32)).to(dev)
+        c = torch.empty_like(a)
+        ms = time_steps(lambda: pm.polymul_negacyclic(a, b, w.q, out=c), steps, warmup)
+        msp = time_steps(lambda: pm.polymul_negacyclic_plain(a, b, w.q, out=c), max(1, steps // 10), 2)
+        out[w.name] = {"polymuls_per_s": a.shape[0] / ms * 1e3, "ms_per_step": ms,
+                       "plain_int_polymuls_per_s": a.shape[0] / msp * 1e3}
+    w = inputs.make_workload(3)
+    groups = []
+    for g in w.groups:
+        ga = torch.from_numpy(g.a.view(np.int32)).to(dev)
+        gb = torch.from_numpy(g.b.view(np.int32)).to(dev)
+        groups.append((ga, gb, torch.empty_like(ga), g.n, g.q))
+    plan = pm.Plan(groups)
+    ms = time_steps(plan.execute, steps, warmup)
+    ops = sum(2 * 16 * g.n * g.n * g.count for g in w.groups)
+    out[w.name] = {"polymuls_per_s": w.products() / ms * 1e3, "ms_per_step": ms, "int8_tops": ops / ms / 1e9,
+                   "launch": "one persistent grouped kernel, hipGraph replay"}
+    plan.close()
+    w = inputs.make_workload(4)
+    a = torch.from_numpy(w.a.view(np.int64)).to(dev)
+    b = torch.from_numpy(w.b.view(np.int64)).to(dev)
+    c = torch.empty_like(a)
+    ms = time_steps(lambda: pm.polymul_negacyclic_u64(a, b, w.q, out=c), max(2, steps // 20), 2)
+    ops = 2 * 64 * w.n * w.n * a.shape[0]
+    out[w.name] = {"polymuls_per_s": a.shape[0] / ms * 1e3, "ms_per_step": ms, "int8_tops": ops / ms / 1e9}
+    return out
 
 
 def main():
@@ -87,18 +127,30 @@ def main():
                     help="untimed steps; the shader clock settles within about 100 launches")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--all", action="store_true", help="also time the other workloads (stderr)")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="first copy this many MiB device-to-device (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the products are independent and this build has no "
-              "multi-GPU path (see DESIGN.md for how it would shard). Run with --gpus 1.", file=sys.stderr)
+              "multi-GPU path (DESIGN.md describes how it would shard). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
     import torch
     import paper_2307_06554_amd as pm
-    from paper_2307_06554_amd import inputs
+    from paper_2307_06554_amd import inputs, tune
 
     pm.load_library()
+    tuned = tune.apply()
+    if args.calibrate_copy_mib:
+        words = args.calibrate_copy_mib * (1 << 18)
+        src = torch.ones(words, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     dev = torch.device("cuda:0")
     w = inputs.make_workload(WORKLOAD_INDEX)
     B, L, n = w.a.shape
@@ -106,27 +158,24 @@ def main():
     a = torch.from_numpy(w.a.view(np.int32)).to(dev)
     b = torch.from_numpy(w.b.view(np.int32)).to(dev)
     c = torch.empty_like(a)
-    stream = torch.cuda.current_stream()
 
-    ms = time_steps(lambda: pm.polymul_negacyclic_rns(a, b, w.qs, out=c), args.steps, args.warmup, stream)
+    ms = time_steps(lambda: pm.polymul_negacyclic_rns(a, b, w.qs, out=c), args.steps, args.warmup)
     value = products / (ms / 1e3)
 
-    # plain integer kernel on the same inputs, one channel at a time (same total work);
-    # channel slices are copied once up front so the timed region holds only the kernel
+    # the plain integer kernel on the same inputs, one channel at a time (same total work);
+    # channel slices are copied once up front so the timed region holds only that kernel
     chans = [(a[:, l].contiguous(), b[:, l].contiguous(), q) for l, q in enumerate(w.qs)]
     cp = torch.empty((B, n), dtype=torch.int32, device=dev)
 
     def plain_run():
         for aa, bb, q in chans:
             pm.polymul_negacyclic_plain(aa, bb, q, out=cp)
-    psteps = max(1, min(args.steps, 5))
-    ms_plain = time_steps(plain_run, psteps, 1, stream)
+    ms_plain = time_steps(plain_run, max(1, min(args.steps, 5)), 1)
     plain_value = products / (ms_plain / 1e3)
 
-    Lm = 4  # int8 limbs per operand for a 30-bit modulus
-    ops_per_product = 2 * Lm * Lm * n * n
+    limbs = 4  # int8 limbs per operand for a 30-bit modulus
+    ops_per_product = 2 * limbs * limbs * n * n
     achieved_tops = ops_per_product * products / (ms / 1e3) / 1e12
-    traffic = measured_traffic("mfma32_resident_kernel_L4")
     out = {
         "metric": METRIC,
         "value": value,
@@ -141,14 +190,17 @@ def main():
         "dtype": "int8",
         "data": "synthetic",
         "config": {"workload": w.name, "n": n, "rns_channels": L, "pairs": B, "products_per_step": products,
-                   "q_bits": 30, "limbs": Lm},
+                   "q_bits": 30, "limbs": limbs, "tile_t": pm.polymul_tune_get(n, limbs), "tune_cache": tuned},
         "roofline": {"bound": "mfma", "achieved": achieved_tops, "peak": PEAK_INT8_TOPS, "unit": "TFLOP/s",
-                     "frac": achieved_tops / PEAK_INT8_TOPS, "traffic": traffic},
+                     "frac": achieved_tops / PEAK_INT8_TOPS, "traffic": measured_traffic(), "kernel": KERNEL},
         "plain_int": {"value": plain_value, "unit": "polymuls/s", "ms_per_step": ms_plain,
                       "mfma_speedup": value / plain_value},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
+    if args.all:
+        print(json.dumps({"other_workloads": other_workloads(max(20, args.steps // 4), 20)}), file=sys.stderr,
+              flush=True)
     print(json.dumps(out), flush=True)
 
 
