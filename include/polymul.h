@@ -79,6 +79,17 @@ polymul_status polymul_negacyclic_rns(const uint32_t* a, const uint32_t* b, uint
                                       uint64_t batch, hipStream_t stream);
 
 /*
+ * Cyclic ring Z_q[x]/(x^n - 1), the other ring the paper names (Sec. 2.1;
+ * Sec. 2.5 notes the method adapts to it): x^n = +1, so the wrapped terms of
+ * the matrix form keep their sign.  Same arguments, layout and errors as
+ * polymul_negacyclic / polymul_negacyclic_u64.
+ */
+polymul_status polymul_cyclic(const uint32_t* a, const uint32_t* b, uint32_t* c,
+                              uint64_t n, uint32_t q, uint64_t batch, hipStream_t stream);
+polymul_status polymul_cyclic_u64(const uint64_t* a, const uint64_t* b, uint64_t* c,
+                                  uint64_t n, uint64_t q, uint64_t batch, hipStream_t stream);
+
+/*
  * The same product as polymul_negacyclic computed with plain 32x32->64-bit
  * integer multiply-adds (schoolbook, no matrix units).  A comparison baseline
  * for the MFMA path; never used as a fallback.
@@ -119,6 +130,37 @@ polymul_status polymul_plan_create(polymul_plan** plan, const polymul_group* gro
                                    uint32_t ngroups, uint32_t flags);
 polymul_status polymul_plan_execute(polymul_plan* plan, hipStream_t stream);
 polymul_status polymul_plan_destroy(polymul_plan* plan);
+
+/*
+ * Karatsuba's three-for-four trade (paper Sec. 4, the Karatsuba paragraph) on
+ * top of the matrix product.  The paper splits each operand into a low and a
+ * high half; in Z_q[x]/(x^n+1) this library splits into even and odd halves
+ * instead, a(x) = a_e(x^2) + x a_o(x^2), because the halves then live in
+ * Z_q[z]/(z^(n/2)+1), a ring of the same kind, and
+ *   c_e = a_e b_e + z a_o b_o,   c_o = (a_e + a_o)(b_e + b_o) - a_e b_e - a_o b_o.
+ * `depth` levels of this turn one product of degree bound n into 3^depth
+ * products of degree bound n / 2^depth, which run on the same matrix kernels;
+ * additions and subtractions are done mod q in two element-wise kernels.  The
+ * result equals polymul_negacyclic_rns's word for word.
+ *
+ *   a, b, c, n, q, L, batch: as for polymul_negacyclic_rns (L <= 16; L <= 8
+ *                when n / 2^depth > 8192).
+ *   depth:       1, 2 or 3, with n / 2^depth >= 4.
+ *   workspace:   device, 16-byte aligned, at least
+ *                polymul_karatsuba_workspace_size(...) bytes, owned by the
+ *                caller, not overlapping a, b or c; its contents on entry do
+ *                not matter and on return are unspecified.  Two calls that
+ *                share a workspace must be ordered on one stream.
+ * Errors: EINVAL for bad sizes, depth, moduli or a too small or misaligned
+ * workspace; EALIAS for overlaps; EUNSUPPORTED for L > 8 with
+ * n / 2^depth > 8192.  No memory is allocated.
+ */
+polymul_status polymul_karatsuba_workspace_size(uint64_t n, uint32_t L, uint64_t batch,
+                                                uint32_t depth, uint64_t* bytes);
+polymul_status polymul_negacyclic_rns_karatsuba(const uint32_t* a, const uint32_t* b, uint32_t* c,
+                                                uint64_t n, const uint32_t* q, uint32_t L,
+                                                uint64_t batch, uint32_t depth, void* workspace,
+                                                uint64_t workspace_bytes, hipStream_t stream);
 
 /*
  * Tile table of the LDS-resident 32-bit path (paper Sec. 2.6, matrix dimension

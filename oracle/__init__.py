@@ -45,8 +45,10 @@ def _load():
     lib.oracle_negacyclic_rns_u32.argtypes = [vp, vp, vp, u64, vp, u32, u64]
     lib.oracle_negacyclic_u32_sample.argtypes = [vp, vp, u64, u32, vp, vp, u64, vp]
     lib.oracle_negacyclic_u64_sample.argtypes = [vp, vp, u64, u64, vp, vp, u64, vp]
+    lib.oracle_cyclic_u32.argtypes = [vp, vp, vp, u64, u32, u64]
+    lib.oracle_cyclic_u64.argtypes = [vp, vp, vp, u64, u64, u64]
     for f in (lib.oracle_negacyclic_u32, lib.oracle_negacyclic_u64, lib.oracle_negacyclic_rns_u32,
-              lib.oracle_negacyclic_u32_sample, lib.oracle_negacyclic_u64_sample):
+              lib.oracle_negacyclic_u32_sample, lib.oracle_negacyclic_u64_sample, lib.oracle_cyclic_u32, lib.oracle_cyclic_u64):
         f.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -74,6 +76,25 @@ def negacyclic(a, b, q):
     c = np.empty_like(a)
     lib = _load()
     fn = lib.oracle_negacyclic_u64 if wide else lib.oracle_negacyclic_u32
+    if fn(_ptr(a), _ptr(b), _ptr(c), n, q, batch) != 0:
+        raise ValueError("oracle rejected arguments (n >= 1, q >= 2)")
+    return c
+
+
+def cyclic(a, b, q):
+    """c = a*b in Z_q[x]/(x^n-1) (Sec. 2.1's other ring); uint32 words if q < 2^32, else uint64."""
+    q = int(q)
+    wide = q >= (1 << 32)
+    dt = np.uint64 if wide else np.uint32
+    a = _as(a, dt)
+    b = _as(b, dt)
+    if a.shape != b.shape or a.ndim < 1:
+        raise ValueError("a and b must have the same shape [..., n]")
+    n = a.shape[-1]
+    batch = a.size // n if n else 0
+    c = np.empty_like(a)
+    lib = _load()
+    fn = lib.oracle_cyclic_u64 if wide else lib.oracle_cyclic_u32
     if fn(_ptr(a), _ptr(b), _ptr(c), n, q, batch) != 0:
         raise ValueError("oracle rejected arguments (n >= 1, q >= 2)")
     return c

@@ -24,6 +24,10 @@
  *
  * RNS form (Sec. 2.4): a residue-number-system product is the same definition
  * applied independently to each residue channel with its own modulus.
+ *
+ * Cyclic ring Z_q[x]/(x^n - 1) (Sec. 2.1 names it as the other common ring):
+ * there x^n = +1, so the folded terms are added instead of subtracted:
+ *     c_j = ( sum_{i<=j} a_i b_{j-i} + sum_{i>j} a_i b_{n+j-i} ) mod q.
  */
 #include <stdint.h>
 #include <stddef.h>
@@ -39,19 +43,26 @@ static uint64_t mod_u192(uint64_t hi, u128 lo, uint64_t q) {
     return (uint64_t)r;
 }
 
-/* One coefficient c_j of one product, 32-bit modulus. */
-static uint32_t coeff_u32(const uint32_t* a, const uint32_t* b, uint64_t n, uint32_t q, uint64_t j) {
+/* One coefficient c_j of one product, 32-bit modulus; cyclic adds the folded terms. */
+static uint32_t coeff_u32_ring(const uint32_t* a, const uint32_t* b, uint64_t n, uint32_t q, uint64_t j, int cyclic) {
     u128 pos = 0, neg = 0;
     for (uint64_t i = 0; i <= j; ++i)
         pos += (u128)((uint64_t)(a[i] % q) * (uint64_t)(b[j - i] % q));
     for (uint64_t i = j + 1; i < n; ++i)
         neg += (u128)((uint64_t)(a[i] % q) * (uint64_t)(b[n + j - i] % q));
     uint64_t p = (uint64_t)(pos % q), m = (uint64_t)(neg % q);
+    if (cyclic) return (uint32_t)((p + m) % q);
     return (uint32_t)((p + q - m) % q);
 }
 
-/* One coefficient c_j of one product, 64-bit modulus: 192-bit accumulators. */
-static uint64_t coeff_u64(const uint64_t* a, const uint64_t* b, uint64_t n, uint64_t q, uint64_t j) {
+static uint32_t coeff_u32(const uint32_t* a, const uint32_t* b, uint64_t n, uint32_t q, uint64_t j) {
+    return coeff_u32_ring(a, b, n, q, j, 0);
+}
+
+/* One coefficient c_j of one product, 64-bit modulus: 192-bit accumulators;
+   cyclic adds the folded terms. */
+static uint64_t coeff_u64_ring(const uint64_t* a, const uint64_t* b, uint64_t n, uint64_t q, uint64_t j,
+                               int cyclic) {
     u128 pos = 0, neg = 0;
     uint64_t pos_hi = 0, neg_hi = 0;
     for (uint64_t i = 0; i <= j; ++i) {
@@ -65,7 +76,12 @@ static uint64_t coeff_u64(const uint64_t* a, const uint64_t* b, uint64_t n, uint
         if (neg < t) ++neg_hi;
     }
     uint64_t p = mod_u192(pos_hi, pos, q), m = mod_u192(neg_hi, neg, q);
+    if (cyclic) return (uint64_t)(((u128)p + m) % q);
     return (uint64_t)(((u128)p + q - m) % q);
+}
+
+static uint64_t coeff_u64(const uint64_t* a, const uint64_t* b, uint64_t n, uint64_t q, uint64_t j) {
+    return coeff_u64_ring(a, b, n, q, j, 0);
 }
 
 /* c[batch][n] = a[batch][n] * b[batch][n] in Z_q[x]/(x^n+1), q < 2^32.
@@ -91,6 +107,32 @@ int oracle_negacyclic_u64(const uint64_t* a, const uint64_t* b, uint64_t* c,
     for (int64_t k = 0; k < total; ++k) {
         uint64_t p = (uint64_t)k / n, j = (uint64_t)k % n;
         c[p * n + j] = coeff_u64(a + p * n, b + p * n, n, q, j);
+    }
+    return 0;
+}
+
+/* c[batch][n] = a[batch][n] * b[batch][n] in Z_q[x]/(x^n-1), q < 2^32. */
+int oracle_cyclic_u32(const uint32_t* a, const uint32_t* b, uint32_t* c,
+                      uint64_t n, uint32_t q, uint64_t batch) {
+    if (n < 1 || q < 2 || !a || !b || !c) return -1;
+    int64_t total = (int64_t)(batch * n);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t k = 0; k < total; ++k) {
+        uint64_t p = (uint64_t)k / n, j = (uint64_t)k % n;
+        c[p * n + j] = coeff_u32_ring(a + p * n, b + p * n, n, q, j, 1);
+    }
+    return 0;
+}
+
+/* Same for q < 2^64 with 64-bit words. */
+int oracle_cyclic_u64(const uint64_t* a, const uint64_t* b, uint64_t* c,
+                      uint64_t n, uint64_t q, uint64_t batch) {
+    if (n < 1 || q < 2 || !a || !b || !c) return -1;
+    int64_t total = (int64_t)(batch * n);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < total; ++k) {
+        uint64_t p = (uint64_t)k / n, j = (uint64_t)k % n;
+        c[p * n + j] = coeff_u64_ring(a + p * n, b + p * n, n, q, j, 1);
     }
     return 0;
 }

@@ -7,10 +7,14 @@ tensors.  Nothing here computes a product on the CPU.
 from .binding import (  # noqa: F401
     PolymulError,
     lib_path,
+    polymul_cyclic,
+    polymul_cyclic_u64,
     load_library,
+    polymul_karatsuba_workspace_size,
     polymul_negacyclic,
     polymul_negacyclic_plain,
     polymul_negacyclic_rns,
+    polymul_negacyclic_rns_karatsuba,
     polymul_negacyclic_u64,
     polymul_plan_create,
     polymul_plan_destroy,

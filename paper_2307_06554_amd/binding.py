@@ -28,7 +28,12 @@ _SIGNATURES = {
     "polymul_plan_create": (ctypes.c_int, [ctypes.POINTER(_vp), _vp, _u32, _u32]),
     "polymul_plan_execute": (ctypes.c_int, [_vp, _vp]),
     "polymul_plan_destroy": (ctypes.c_int, [_vp]),
+    "polymul_cyclic": (ctypes.c_int, [_vp, _vp, _vp, _u64, _u32, _u64, _vp]),
+    "polymul_cyclic_u64": (ctypes.c_int, [_vp, _vp, _vp, _u64, _u64, _u64, _vp]),
     "polymul_tune_set": (ctypes.c_int, [_u64, _u32, _u32]),
+    "polymul_karatsuba_workspace_size": (ctypes.c_int, [_u64, _u32, _u64, _u32, ctypes.POINTER(_u64)]),
+    "polymul_negacyclic_rns_karatsuba": (ctypes.c_int, [_vp, _vp, _vp, _u64, _vp, _u32, _u64, _u32, _vp, _u64,
+                                                        _vp]),
     "polymul_tune_get": (ctypes.c_int, [_u64, _u32, ctypes.POINTER(_u32)]),
 }
 
@@ -136,6 +141,31 @@ def polymul_negacyclic_u64(a, b, q, out=None, stream=None):
     return c
 
 
+def _binary(name, a, b, q, out, stream, nbytes):
+    import torch
+    if a.shape != b.shape or a.dim() < 1:
+        raise ValueError("a and b must have the same shape [..., n]")
+    n = a.shape[-1]
+    batch = a.numel() // n if n else 0
+    c = torch.empty_like(a) if out is None else out
+    if c.shape != a.shape:
+        raise ValueError("out has the wrong shape")
+    st = getattr(load_library(), name)(_words(a, nbytes, "a"), _words(b, nbytes, "b"), _words(c, nbytes, "out"),
+                                       n, int(q), batch, _stream(stream))
+    _check(st, name)
+    return c
+
+
+def polymul_cyclic(a, b, q, out=None, stream=None):
+    """c = a*b in Z_q[x]/(x^n-1) for 32-bit words [..., n], q < 2^32."""
+    return _binary("polymul_cyclic", a, b, q, out, stream, 4)
+
+
+def polymul_cyclic_u64(a, b, q, out=None, stream=None):
+    """c = a*b in Z_q[x]/(x^n-1) for 64-bit words [..., n], q < 2^64."""
+    return _binary("polymul_cyclic_u64", a, b, q, out, stream, 8)
+
+
 def polymul_negacyclic_rns(a, b, qs, out=None, stream=None):
     """RNS form: a, b are 32-bit words [batch, L, n]; channel l is taken mod qs[l]."""
     import torch
@@ -149,6 +179,36 @@ def polymul_negacyclic_rns(a, b, qs, out=None, stream=None):
     st = load_library().polymul_negacyclic_rns(_words(a, 4, "a"), _words(b, 4, "b"), _words(c, 4, "out"),
                                               n, ctypes.cast(qarr, ctypes.c_void_p), L, batch, _stream(stream))
     _check(st, "polymul_negacyclic_rns")
+    return c
+
+
+def polymul_karatsuba_workspace_size(n, L, batch, depth):
+    """Bytes of device workspace polymul_negacyclic_rns_karatsuba needs."""
+    out = ctypes.c_uint64()
+    _check(load_library().polymul_karatsuba_workspace_size(int(n), int(L), int(batch), int(depth),
+                                                           ctypes.byref(out)), "polymul_karatsuba_workspace_size")
+    return out.value
+
+
+def polymul_negacyclic_rns_karatsuba(a, b, qs, depth, workspace=None, out=None, stream=None):
+    """polymul_negacyclic_rns through `depth` Karatsuba levels.  workspace: a device
+    tensor of at least polymul_karatsuba_workspace_size bytes (allocated here if None)."""
+    import torch
+    if a.shape != b.shape or a.dim() != 3:
+        raise ValueError("a and b must be [batch, L, n]")
+    batch, L, n = a.shape
+    if len(qs) != L:
+        raise ValueError("need one modulus per channel")
+    c = torch.empty_like(a) if out is None else out
+    need = polymul_karatsuba_workspace_size(n, L, batch, depth)
+    if workspace is None:
+        workspace = torch.empty(max(need, 16), dtype=torch.uint8, device=a.device)
+    ws_bytes = workspace.numel() * workspace.element_size()
+    qarr = (ctypes.c_uint32 * L)(*[int(x) for x in qs])
+    st = load_library().polymul_negacyclic_rns_karatsuba(
+        _words(a, 4, "a"), _words(b, 4, "b"), _words(c, 4, "out"), n, ctypes.cast(qarr, ctypes.c_void_p), L,
+        batch, int(depth), ctypes.c_void_p(workspace.data_ptr()), ws_bytes, _stream(stream))
+    _check(st, "polymul_negacyclic_rns_karatsuba")
     return c
 
 

@@ -47,9 +47,11 @@ struct Mfma32Params {
   uint32_t slot_bytes;   // L * (a_plane + b_plane)
   uint32_t E;            // ext index held at reversed position 0
   // Product i of this launch is global product (i / lc) * nq_total + l0 + (i % lc)
-  // and uses modulus mods[i % lc].
-  uint32_t lc, nq_total, l0;
+  // and uses modulus mods[i % lc]; with lrep > 1 (dense sub-product batches)
+  // product i is global product i and uses modulus mods[(i / lrep) % lc].
+  uint32_t lc, nq_total, l0, lrep;
   uint32_t fast_epilogue;  // 1: sum_s T_s * rcent[s] is known to stay below 2^62 in magnitude
+  uint32_t cyclic;         // 1: ring Z_q[x]/(x^n - 1): wrapped terms keep their sign
   ModQ32 mods[kMaxQ];
   int32_t rcent[kMaxQ][8];  // 2^(8s) mod q as a centred residue, s < 2L-1
 };
@@ -161,7 +163,10 @@ __device__ __forceinline__ void mfma32_stage(const Mfma32Params& P, uint8_t* slo
       const int idx = (int)P.E - (dw * 4 + k);
       uint32_t dg = 0;
       if (idx >= 0 && idx < n) dg = digits32<L>(reduce_u32(A[idx], m), q, thr);
-      else if (idx < 0 && idx > -n) dg = neg_digits32<L>(reduce_u32(A[n + idx], m), q, thr);
+      else if (idx < 0 && idx > -n) {
+        const uint32_t xr = reduce_u32(A[n + idx], m);
+        dg = P.cyclic ? digits32<L>(xr, q, thr) : neg_digits32<L>(xr, q, thr);
+      }
       w[k] = dg;
     }
     transpose_store<L>(slot, P.a_plane, dw * 4, w);
@@ -177,7 +182,10 @@ __device__ __forceinline__ void mfma32_stage(const Mfma32Params& P, uint8_t* slo
       uint32_t dg = 0;
       if (ww < t) {
         if (v >= 0 && v < r) dg = digits32<L>(reduce_u32(B[v * t + ww], m), q, thr);
-        else if (v < 0 && v > -r) dg = neg_digits32<L>(reduce_u32(B[(v + r) * t + ww], m), q, thr);
+        else if (v < 0 && v > -r) {
+          const uint32_t xr = reduce_u32(B[(v + r) * t + ww], m);
+          dg = P.cyclic ? digits32<L>(xr, q, thr) : neg_digits32<L>(xr, q, thr);
+        }
       }
       w[k] = dg;
     }
@@ -319,6 +327,10 @@ struct GroupInfo {
 };
 
 __device__ __forceinline__ uint64_t global_product(const Mfma32Params& P, uint64_t prod, uint32_t* li) {
+  if (P.lrep > 1) {
+    *li = (uint32_t)((prod / P.lrep) % P.lc);
+    return prod;
+  }
   *li = (uint32_t)(prod % P.lc);
   return (prod / P.lc) * P.nq_total + P.l0 + *li;
 }
@@ -374,7 +386,7 @@ __device__ __forceinline__ void item_store(const Mfma32Params& P, const GroupInf
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       w[k] = digits32<L>(xr[3 - k], q, thr);
-      nw[k] = neg_digits32<L>(xr[3 - k], q, thr);
+      nw[k] = P.cyclic ? w[k] : neg_digits32<L>(xr[3 - k], q, thr);
     }
     const uint32_t dw = ((P.E + 1) >> 2) - 1 - j;
     transpose_store<L>(slot, P.a_plane, dw * 4, w);
@@ -386,7 +398,7 @@ __device__ __forceinline__ void item_store(const Mfma32Params& P, const GroupInf
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       w[k] = digits32<L>(xr[k], q, thr);
-      nw[k] = neg_digits32<L>(xr[k], q, thr);
+      nw[k] = P.cyclic ? w[k] : neg_digits32<L>(xr[k], q, thr);
     }
     uint8_t* bbase = slot + L * P.a_plane;
     const int rp = vs - gi.v_lo, rn = vs - (int)P.r - gi.v_lo;

@@ -42,6 +42,8 @@ struct StreamParams {
   uint32_t a_win;         // bytes per limb of one A window buffer
   uint32_t lds_b;         // LDS offset of the B ring
   uint32_t lc, nq_total, l0;  // product i -> global (i/lc)*nq_total + l0 + i%lc, modulus i%lc
+  uint32_t lrep;              // > 1: product i is global i with modulus (i/lrep)%lc
+  uint32_t cyclic;            // 1: ring Z_q[x]/(x^n - 1): wrapped terms keep their sign
   ModQ64 mods[kMaxQS];
 };
 
@@ -153,14 +155,14 @@ __device__ __forceinline__ const W* item_ptr(const StreamParams& P, const Stream
     const int i0 = 4 * it.e;
     if (n < 4) return nullptr;  // handled element-wise
     if (i0 >= 0 && i0 < n) return (const W*)P.a + gp * P.n + i0;
-    if (i0 < 0 && i0 >= -n) { *neg = true; return (const W*)P.a + gp * P.n + (n + i0); }
+    if (i0 < 0 && i0 >= -n) { *neg = !P.cyclic; return (const W*)P.a + gp * P.n + (n + i0); }
     return nullptr;
   }
   if (it.kind == 2) {
     const int v = it.e, w = 4 * it.k;
     if (t < 4 || w >= t) return nullptr;
     if (v >= 0 && v < r) return (const W*)P.b + gp * P.n + (size_t)v * t + w;
-    if (v < 0 && v > -r) { *neg = true; return (const W*)P.b + gp * P.n + (size_t)(v + r) * t + w; }
+    if (v < 0 && v > -r) { *neg = !P.cyclic; return (const W*)P.b + gp * P.n + (size_t)(v + r) * t + w; }
   }
   return nullptr;
 }
@@ -179,7 +181,10 @@ __device__ __forceinline__ void item_write(const StreamParams& P, const StreamIt
       for (int k = 0; k < 4; ++k) {
         const int idx = i0 + k;
         if (idx >= 0 && idx < n) d[k] = digits64<L>(word_reduce<W>(((const W*)P.a)[gp * P.n + idx], m), m);
-        else if (idx < 0 && idx > -n) d[k] = neg_digits64<L>(word_reduce<W>(((const W*)P.a)[gp * P.n + n + idx], m), m);
+        else if (idx < 0 && idx > -n) {
+          const uint64_t xr = word_reduce<W>(((const W*)P.a)[gp * P.n + n + idx], m);
+          d[k] = P.cyclic ? digits64<L>(xr, m) : neg_digits64<L>(xr, m);
+        }
       }
     } else if (live) {
 #pragma unroll
@@ -199,8 +204,10 @@ __device__ __forceinline__ void item_write(const StreamParams& P, const StreamIt
         const int ww = w + k;
         if (ww >= t) continue;
         if (v >= 0 && v < r) d[k] = digits64<L>(word_reduce<W>(((const W*)P.b)[gp * P.n + (size_t)v * t + ww], m), m);
-        else if (v < 0 && v > -r)
-          d[k] = neg_digits64<L>(word_reduce<W>(((const W*)P.b)[gp * P.n + (size_t)(v + r) * t + ww], m), m);
+        else if (v < 0 && v > -r) {
+          const uint64_t xr = word_reduce<W>(((const W*)P.b)[gp * P.n + (size_t)(v + r) * t + ww], m);
+          d[k] = P.cyclic ? digits64<L>(xr, m) : neg_digits64<L>(xr, m);
+        }
       }
     } else if (live) {
 #pragma unroll
@@ -246,8 +253,8 @@ template <int L, typename W>
 __device__ __forceinline__ void stream_block(const StreamParams& P, uint64_t wg, uint8_t* smem) {
   const uint64_t prod = wg / P.ublocks;
   const int U0 = 64 * (int)(wg - prod * P.ublocks);
-  const uint32_t li = (uint32_t)(prod % P.lc);
-  const uint64_t gp = (prod / P.lc) * P.nq_total + P.l0 + li;
+  const uint32_t li = P.lrep > 1 ? (uint32_t)((prod / P.lrep) % P.lc) : (uint32_t)(prod % P.lc);
+  const uint64_t gp = P.lrep > 1 ? prod : (prod / P.lc) * P.nq_total + P.l0 + li;
   const ModQ64& m = P.mods[li];
   uint8_t* ring = smem + P.lds_b;
   const int wave = (int)(threadIdx.x >> 6);

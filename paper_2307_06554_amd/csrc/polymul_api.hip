@@ -14,6 +14,7 @@
 #include "pm_plain.h"
 #include "pm_stream.h"
 #include "pm_grouped.h"
+#include "pm_karatsuba.h"
 #include "pm_wide_host.h"
 
 using namespace pm;
@@ -144,7 +145,7 @@ int limbs32(const uint32_t* qs, uint32_t lc) {
 // Resident-kernel parameters; *lds gets the dynamic LDS bytes per workgroup.
 polymul_status fill_mfma32(Mfma32Params& P, const uint32_t* a, const uint32_t* b, uint32_t* c, uint32_t n,
                            const uint32_t* qs, uint32_t lc, uint32_t nq_total, uint32_t l0, uint64_t nprod, int L,
-                           uint32_t t, uint32_t* lds) {
+                           uint32_t t, uint32_t* lds, bool cyclic = false, uint32_t lrep = 1) {
   if (!tile_ok(n, t)) return POLYMUL_EINVAL;
   const Geometry32 g = geometry32(n, t);
   P = Mfma32Params{};
@@ -159,7 +160,7 @@ polymul_status fill_mfma32(Mfma32Params& P, const uint32_t* a, const uint32_t* b
   P.slots = g.slots;
   P.a_plane = g.a_plane; P.b_rows = g.b_rows; P.b_rowstride = g.b_rowstride; P.b_plane = g.b_plane;
   P.E = g.E;
-  P.lc = lc; P.nq_total = nq_total; P.l0 = l0;
+  P.lc = lc; P.nq_total = nq_total; P.l0 = l0; P.lrep = lrep;
   P.slot_bytes = (uint32_t)L * (g.a_plane + g.b_plane);
   // Epilogue choice: the one-reduction form needs sum_s P_s * n * 2^14 * |rcent_s| < 2^62,
   // P_s = number of limb pairs (i, j) with i + j = s.
@@ -179,6 +180,7 @@ polymul_status fill_mfma32(Mfma32Params& P, const uint32_t* a, const uint32_t* b
     if (bound >= ((unsigned __int128)1 << 62)) fast = false;
   }
   P.fast_epilogue = fast ? 1u : 0u;
+  P.cyclic = cyclic ? 1u : 0u;
   *lds = P.slots * P.slot_bytes;
   return *lds <= kMaxLds ? POLYMUL_OK : POLYMUL_EUNSUPPORTED;
 }
@@ -213,7 +215,8 @@ int limbs64(const uint64_t* qs, uint32_t lc) {
 }
 
 polymul_status fill_stream(StreamParams& P, const void* a, const void* b, void* c, uint32_t n, const uint64_t* qs,
-                           uint32_t lc, uint32_t nq_total, uint32_t l0, uint64_t nprod, int L, uint32_t* lds) {
+                           uint32_t lc, uint32_t nq_total, uint32_t l0, uint64_t nprod, int L, uint32_t* lds,
+                           bool cyclic = false, uint32_t lrep = 1) {
   P = StreamParams{};
   P.a = a; P.b = b; P.c = c;
   P.nprod = nprod;
@@ -234,7 +237,8 @@ polymul_status fill_stream(StreamParams& P, const void* a, const void* b, void* 
   P.flush_every = fe < 1 ? 1 : fe;
   P.a_win = ((P.dc - 1) * P.t + 32 * P.tz + P.rowlen + 4 + 15) & ~15u;
   P.lds_b = 2u * (uint32_t)L * P.a_win;
-  P.lc = lc; P.nq_total = nq_total; P.l0 = l0;
+  P.lc = lc; P.nq_total = nq_total; P.l0 = l0; P.lrep = lrep;
+  P.cyclic = cyclic ? 1u : 0u;
   for (uint32_t i = 0; i < lc; ++i) P.mods[i] = make_mod64(qs[i], L);
   *lds = P.lds_b + (uint32_t)L * kRing * P.rs;
   return *lds <= kMaxLds ? POLYMUL_OK : POLYMUL_EUNSUPPORTED;
@@ -252,12 +256,13 @@ polymul_status launch_stream_L(const StreamParams& P, uint32_t lds, hipStream_t 
 // nprod products of degree bound n (i -> global (i/lc)*nq_total + l0 + i%lc), moduli qs[0..lc <= kMaxQS).
 template <typename W>
 polymul_status run_stream(const W* a, const W* b, W* c, uint32_t n, const uint64_t* qs, uint32_t lc,
-                          uint32_t nq_total, uint32_t l0, uint64_t nprod, hipStream_t s) {
+                          uint32_t nq_total, uint32_t l0, uint64_t nprod, hipStream_t s, bool cyclic = false,
+                          uint32_t lrep = 1) {
   const int L = limbs64(qs, lc);
   if (sizeof(W) == 4 && L > 4) return POLYMUL_EINVAL;
   StreamParams P;
   uint32_t lds;
-  polymul_status st = fill_stream(P, a, b, c, n, qs, lc, nq_total, l0, nprod, L, &lds);
+  polymul_status st = fill_stream(P, a, b, c, n, qs, lc, nq_total, l0, nprod, L, &lds, cyclic, lrep);
   if (st != POLYMUL_OK) return st;
   if (L == 4) return launch_stream_L<4, W, 2>(P, lds, s);
   return launch_stream_L<8, W, 1>(P, lds, s);
@@ -265,8 +270,15 @@ polymul_status run_stream(const W* a, const W* b, W* c, uint32_t n, const uint64
 
 // nprod products (i -> global (i/lc)*nq_total + l0 + i%lc) with moduli qs[0..lc <= kMaxQ).
 polymul_status run_mfma32(const uint32_t* a, const uint32_t* b, uint32_t* c, uint32_t n, const uint32_t* qs,
-                          uint32_t lc, uint32_t nq_total, uint32_t l0, uint64_t nprod, hipStream_t s) {
+                          uint32_t lc, uint32_t nq_total, uint32_t l0, uint64_t nprod, hipStream_t s,
+                          bool cyclic = false, uint32_t lrep = 1) {
   if (n > 8192) {
+    if (lrep > 1) {
+      if (lc > (uint32_t)kMaxQS) return POLYMUL_EUNSUPPORTED;
+      uint64_t q64[kMaxQS];
+      for (uint32_t i = 0; i < lc; ++i) q64[i] = qs[i];
+      return run_stream<uint32_t>(a, b, c, n, q64, lc, nq_total, l0, nprod, s, cyclic, lrep);
+    }
     // degree too large for both operands in LDS: K-streaming kernel, moduli in chunks of kMaxQS
     uint64_t q64[kMaxQ];
     for (uint32_t i = 0; i < lc; ++i) q64[i] = qs[i];
@@ -274,7 +286,7 @@ polymul_status run_mfma32(const uint32_t* a, const uint32_t* b, uint32_t* c, uin
     for (uint32_t c0 = 0; c0 < lc; c0 += kMaxQS) {
       const uint32_t cc = std::min(lc - c0, (uint32_t)kMaxQS);
       const uint64_t np = cc == lc ? nprod : batch * cc;
-      polymul_status st = run_stream<uint32_t>(a, b, c, n, q64 + c0, cc, nq_total, l0 + c0, np, s);
+      polymul_status st = run_stream<uint32_t>(a, b, c, n, q64 + c0, cc, nq_total, l0 + c0, np, s, cyclic);
       if (st != POLYMUL_OK) return st;
     }
     return POLYMUL_OK;
@@ -282,7 +294,7 @@ polymul_status run_mfma32(const uint32_t* a, const uint32_t* b, uint32_t* c, uin
   const int L = limbs32(qs, lc);
   Mfma32Params P;
   uint32_t lds;
-  polymul_status st = fill_mfma32(P, a, b, c, n, qs, lc, nq_total, l0, nprod, L, tile_for(n, L), &lds);
+  polymul_status st = fill_mfma32(P, a, b, c, n, qs, lc, nq_total, l0, nprod, L, tile_for(n, L), &lds, cyclic, lrep);
   if (st != POLYMUL_OK) return st;
   const bool small = n < 4;
   switch (L) {
@@ -534,6 +546,85 @@ polymul_status polymul_plan_execute(polymul_plan* plan, hipStream_t stream) {
 polymul_status polymul_plan_destroy(polymul_plan* plan) {
   plan_free(plan);
   return POLYMUL_OK;
+}
+
+polymul_status polymul_cyclic(const uint32_t* a, const uint32_t* b, uint32_t* c, uint64_t n, uint32_t q,
+                              uint64_t batch, hipStream_t stream) {
+  if (q < 2) return POLYMUL_EINVAL;
+  uint64_t bytes;
+  polymul_status st = check_arrays(a, b, c, n, batch, 1, 4, &bytes);
+  if (st != POLYMUL_OK || batch == 0) return st;
+  return run_mfma32(a, b, c, (uint32_t)n, &q, 1, 1, 0, batch, stream, true);
+}
+
+polymul_status polymul_cyclic_u64(const uint64_t* a, const uint64_t* b, uint64_t* c, uint64_t n, uint64_t q,
+                                  uint64_t batch, hipStream_t stream) {
+  if (q < 2) return POLYMUL_EINVAL;
+  uint64_t bytes;
+  polymul_status st = check_arrays(a, b, c, n, batch, 1, 8, &bytes);
+  if (st != POLYMUL_OK || batch == 0) return st;
+  return run_stream<uint64_t>(a, b, c, (uint32_t)n, &q, 1, 1, 0, batch, stream, true);
+}
+
+polymul_status polymul_karatsuba_workspace_size(uint64_t n, uint32_t L, uint64_t batch, uint32_t depth,
+                                                uint64_t* bytes) {
+  if (!bytes || depth < 1 || depth > 3 || L < 1 || L > 16 || !is_pow2(n) || n > 65536 || (n >> depth) < 4)
+    return POLYMUL_EINVAL;
+  uint64_t nsub = 1;
+  for (uint32_t l = 0; l < depth; ++l) nsub *= 3;
+  const unsigned __int128 words = (unsigned __int128)batch * L * nsub * (n >> depth);
+  if (words >> 58) return POLYMUL_EINVAL;
+  *bytes = (uint64_t)(3 * words * 4);
+  return POLYMUL_OK;
+}
+
+polymul_status polymul_negacyclic_rns_karatsuba(const uint32_t* a, const uint32_t* b, uint32_t* c, uint64_t n,
+                                                const uint32_t* q, uint32_t L, uint64_t batch, uint32_t depth,
+                                                void* workspace, uint64_t workspace_bytes, hipStream_t stream) {
+  if (L == 0 || !q) return POLYMUL_EINVAL;
+  for (uint32_t l = 0; l < L; ++l)
+    if (q[l] < 2) return POLYMUL_EINVAL;
+  uint64_t need;
+  polymul_status st = polymul_karatsuba_workspace_size(n, L, batch, depth, &need);
+  if (st != POLYMUL_OK) return st;
+  uint64_t bytes;
+  st = check_arrays(a, b, c, n, batch, L, 4, &bytes);
+  if (st != POLYMUL_OK || batch == 0) return st;
+  if (!workspace || ((uintptr_t)workspace & 15) || workspace_bytes < need) return POLYMUL_EINVAL;
+  if (overlaps(workspace, need, a, bytes) || overlaps(workspace, need, b, bytes) || overlaps(workspace, need, c, bytes))
+    return POLYMUL_EALIAS;
+  const uint32_t nsub = depth == 1 ? 3 : depth == 2 ? 9 : 27;
+  const uint32_t np = (uint32_t)(n >> depth);
+  const uint64_t nprod = batch * L;
+  const uint64_t sub_words = nprod * nsub * np;
+  KaraParams K{};
+  K.a = a; K.b = b; K.c = c;
+  K.sa = (uint32_t*)workspace;
+  K.sb = K.sa + sub_words;
+  uint32_t* sc = K.sb + sub_words;
+  K.sc = sc;
+  K.nprod = nprod; K.n = (uint32_t)n; K.np = np; K.depth = depth; K.nsub = nsub; K.L = L;
+  const int Lq = limbs32(q, L);
+  for (uint32_t l = 0; l < L; ++l) K.mods[l] = make_mod32(q[l], Lq);
+  const uint64_t threads = nprod * np;
+  const uint64_t blocks = (threads + 255) / 256;
+  if (blocks > 0x7FFFFFFFull) return POLYMUL_EUNSUPPORTED;
+  switch (depth) {
+    case 1: hipLaunchKernelGGL(kara_split_kernel<1>, dim3((uint32_t)blocks), dim3(256), 0, stream, K); break;
+    case 2: hipLaunchKernelGGL(kara_split_kernel<2>, dim3((uint32_t)blocks), dim3(256), 0, stream, K); break;
+    default: hipLaunchKernelGGL(kara_split_kernel<3>, dim3((uint32_t)blocks), dim3(256), 0, stream, K); break;
+  }
+  st = launch_status();
+  if (st != POLYMUL_OK) return st;
+  // the sub-products: nprod * nsub products of degree bound n' with modulus (i / nsub) % L
+  st = run_mfma32(K.sa, K.sb, sc, np, q, L, L, 0, nprod * nsub, stream, false, nsub);
+  if (st != POLYMUL_OK) return st;
+  switch (depth) {
+    case 1: hipLaunchKernelGGL(kara_combine_kernel<1>, dim3((uint32_t)blocks), dim3(256), 0, stream, K); break;
+    case 2: hipLaunchKernelGGL(kara_combine_kernel<2>, dim3((uint32_t)blocks), dim3(256), 0, stream, K); break;
+    default: hipLaunchKernelGGL(kara_combine_kernel<3>, dim3((uint32_t)blocks), dim3(256), 0, stream, K); break;
+  }
+  return launch_status();
 }
 
 polymul_status polymul_tune_set(uint64_t n, uint32_t L, uint32_t t) {

@@ -144,3 +144,34 @@ def test_binding_refuses_host_tensors():
     import torch
     with pytest.raises(TypeError):
         pm.polymul_negacyclic(torch.zeros(4, dtype=torch.int32), torch.zeros(4, dtype=torch.int32), 17)
+
+
+def test_karatsuba_workspace_size():
+    for n, L, batch, depth in ((4096, 8, 16, 2), (64, 1, 3, 1), (65536, 2, 1, 3), (32, 4, 2, 3)):
+        words = batch * L * 3 ** depth * (n >> depth)
+        assert pm.polymul_karatsuba_workspace_size(n, L, batch, depth) == 3 * 4 * words
+    for n, L, depth in ((4096, 8, 0), (4096, 8, 4), (16, 1, 3), (100, 1, 1), (4096, 0, 1), (4096, 17, 1),
+                        (131072, 1, 1)):
+        with pytest.raises(pm.PolymulError):
+            pm.polymul_karatsuba_workspace_size(n, L, 1, depth)
+
+
+def test_karatsuba_arguments():
+    qs = (ctypes.c_uint32 * 2)(17, 19)
+    qp = ctypes.cast(qs, ctypes.c_void_p)
+    W = 0x40000000
+    need = pm.polymul_karatsuba_workspace_size(256, 2, 1, 2)
+    k = "polymul_negacyclic_rns_karatsuba"
+    assert call(k, A, B, C, 256, qp, 2, 1, 2, W, need - 1, None) == EINVAL   # workspace too small
+    assert call(k, A, B, C, 256, qp, 2, 1, 2, W + 4, need, None) == EINVAL   # misaligned workspace
+    assert call(k, A, B, C, 256, qp, 2, 1, 2, None, need, None) == EINVAL    # no workspace
+    assert call(k, A, B, C, 256, qp, 2, 1, 0, W, need, None) == EINVAL       # depth 0
+    assert call(k, A, B, C, 256, qp, 2, 1, 4, W, 1 << 30, None) == EINVAL    # depth 4
+    assert call(k, A, B, C, 8, qp, 2, 1, 2, W, need, None) == EINVAL         # n / 2^depth < 4
+    assert call(k, A, B, C, 256, None, 2, 1, 2, W, need, None) == EINVAL
+    bad = (ctypes.c_uint32 * 2)(17, 1)
+    assert call(k, A, B, C, 256, ctypes.cast(bad, ctypes.c_void_p), 2, 1, 2, W, need, None) == EINVAL
+    assert call(k, A, B, A, 256, qp, 2, 1, 2, W, need, None) == EALIAS         # c overlaps a
+    assert call(k, A, B, C, 256, qp, 2, 1, 2, A - 16, need, None) == EALIAS    # workspace overlaps a
+    assert call(k, A, B, C, 256, qp, 2, 1, 2, C + 64, need, None) == EALIAS    # workspace overlaps c
+    assert call(k, None, None, None, 256, qp, 2, 0, 2, None, 0, None) == 0     # empty batch

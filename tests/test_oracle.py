@@ -209,3 +209,85 @@ def test_correct_python_definition_passes_all_pins():
 def test_planted_mistakes_are_caught(mistake):
     failures = pins.run_all(_python_definition(mistake))
     assert failures, f"planted mistake '{mistake}' passed every pin"
+
+
+# --------------------------------------------------- cyclic ring x^n - 1
+def cyc(a, b, q):
+    return oracle.cyclic(a, b, q)
+
+
+@pytest.mark.parametrize("q", [2, 3329, Q30, Q32])
+@pytest.mark.parametrize("n", [1, 3, 8, 64])
+def test_cyclic_kronecker_and_long_division(n, q):
+    """Kronecker substitution for the Z[x] product, remainder by x^n - 1."""
+    rng = random.Random(n * 31 + q % 1009)
+    a = [rng.randrange(q) for _ in range(n)]
+    b = [rng.randrange(q) for _ in range(n)]
+    k = (n * (q - 1) ** 2).bit_length() + 1
+    P = sum(v << (k * i) for i, v in enumerate(a)) * sum(v << (k * i) for i, v in enumerate(b))
+    prod = [(P >> (k * d)) & ((1 << k) - 1) for d in range(2 * n - 1)]
+    want = [v % q for v in pins.poly_rem_monic(prod, [-1] + [0] * (n - 1) + [1])]
+    got = cyc(np.array([a], dtype=np.uint64).astype(np.uint32), np.array([b], dtype=np.uint64).astype(np.uint32), q)[0]
+    assert [int(v) for v in got] == want
+
+
+def test_cyclic_monomial_is_plain_rotation():
+    rng = np.random.Generator(np.random.PCG64(5))
+    n, q = 64, Q30
+    a = rng.integers(0, q, size=(1, n), dtype=np.uint64).astype(np.uint32)
+    for k in (0, 1, 17, n - 1):
+        b = np.zeros((1, n), dtype=np.uint32)
+        b[0, k] = 1
+        assert np.array_equal(cyc(a, b, q)[0], np.roll(a[0], k))
+    # x^(n-1) * x = x^n = 1
+    a = np.zeros((1, n), dtype=np.uint32)
+    a[0, n - 1] = 1
+    b = np.zeros((1, n), dtype=np.uint32)
+    b[0, 1] = 1
+    want = np.zeros(n, dtype=np.uint32)
+    want[0] = 1
+    assert np.array_equal(cyc(a, b, q)[0], want)
+
+
+def test_cyclic_evaluation_at_roots_of_unity():
+    """For q = 1 mod n, c(w^i) = a(w^i) b(w^i) at every n-th root of unity w^i."""
+    n, q = 64, 7681  # 7681 = 1 + 120 * 64
+    rng = random.Random(11)
+    g = 17
+    w = pow(g, (q - 1) // n, q)
+    while pow(w, n // 2, q) == 1:
+        g += 1
+        w = pow(g, (q - 1) // n, q)
+    a = [rng.randrange(q) for _ in range(n)]
+    b = [rng.randrange(q) for _ in range(n)]
+    c = [int(v) for v in cyc(np.array([a], dtype=np.uint32), np.array([b], dtype=np.uint32), q)[0]]
+    for i in range(n):
+        x = pow(w, i, q)
+        assert pins.poly_eval(c, x, q) == pins.poly_eval(a, x, q) * pins.poly_eval(b, x, q) % q
+
+
+def test_cyclic_bruteforce_tiny():
+    import itertools
+    for n, q in ((2, 3), (4, 2), (3, 3)):
+        vecs = list(itertools.product(range(q), repeat=n))
+        A = np.array([v for v in vecs for _ in vecs], dtype=np.uint32)
+        B = np.array([w for _ in vecs for w in vecs], dtype=np.uint32)
+        C = cyc(A, B, q)
+        mod = [-1] + [0] * (n - 1) + [1]
+        for r in range(A.shape[0]):
+            want = [v % q for v in pins.poly_rem_monic(pins.zpoly_mul(list(A[r].astype(int)), list(B[r].astype(int))), mod)]
+            assert [int(v) for v in C[r]] == want
+
+
+@pytest.mark.parametrize("q", [GOLD_Q, (1 << 64) - 59, (1 << 40) + 15])
+def test_cyclic_u64_kronecker(q):
+    rng = random.Random(q % 997)
+    for n in (1, 4, 32):
+        a = [rng.randrange(q) for _ in range(n)]
+        b = [rng.randrange(q) for _ in range(n)]
+        k = (n * (q - 1) ** 2).bit_length() + 1
+        P = sum(v << (k * i) for i, v in enumerate(a)) * sum(v << (k * i) for i, v in enumerate(b))
+        prod = [(P >> (k * d)) & ((1 << k) - 1) for d in range(2 * n - 1)]
+        want = [v % q for v in pins.poly_rem_monic(prod, [-1] + [0] * (n - 1) + [1])]
+        got = oracle.cyclic(np.array([a], dtype=np.uint64), np.array([b], dtype=np.uint64), q)[0]
+        assert [int(v) for v in got] == want
