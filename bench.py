@@ -5,7 +5,9 @@ One step = one pass of the whole path over one batch: the n = 4096 RNS workload
 (256 ciphertext-like pairs x 8 residue channels with distinct 30-bit primes
 q_i = 1 mod 2n, i.e. 2048 independent limb-products) through
 polymul_negacyclic_rns, inputs already resident in HBM.  Prints one JSON line
-on stdout.  --all also times the other workloads (to stderr).
+on stdout.  The same batch also goes through the Karatsuba route
+(polymul_negacyclic_rns_karatsuba, reported beside the headline) and the plain
+integer kernel.  --all also times the other workloads (to stderr).
 """
 import argparse
 import hashlib
@@ -128,6 +130,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--all", action="store_true", help="also time the other workloads (stderr)")
+    ap.add_argument("--karatsuba-depth", type=int, default=2, help="0 skips the Karatsuba route")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first copy this many MiB device-to-device (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -173,6 +176,22 @@ def main():
     ms_plain = time_steps(plain_run, max(1, min(args.steps, 5)), 1)
     plain_value = products / (ms_plain / 1e3)
 
+    kara = None
+    if args.karatsuba_depth:
+        d = args.karatsuba_depth
+        ws = torch.empty(pm.polymul_karatsuba_workspace_size(n, L, B, d), dtype=torch.uint8, device=dev)
+        ck = torch.empty_like(a)
+        ms_k = time_steps(lambda: pm.polymul_negacyclic_rns_karatsuba(a, b, w.qs, d, workspace=ws, out=ck),
+                          args.steps, args.warmup)
+        pm.polymul_negacyclic_rns(a, b, w.qs, out=c)
+        torch.cuda.synchronize()
+        sub_ops = 2 * 16 * (n >> d) ** 2 * 3 ** d * products
+        kara = {"depth": d, "value": products / (ms_k / 1e3), "unit": "polymuls/s", "ms_per_step": ms_k,
+                "speedup_vs_direct": ms / ms_k, "bit_identical_to_direct": bool(torch.equal(ck, c)),
+                "kernels": "split, mfma32_group_kernel on 3^d sub-products of degree n/2^d, combine",
+                "mfma_ops_per_step": sub_ops, "schoolbook_equivalent_tops": 2 * 16 * n * n * products / ms_k / 1e9}
+        del ws, ck
+
     limbs = 4  # int8 limbs per operand for a 30-bit modulus
     ops_per_product = 2 * limbs * limbs * n * n
     achieved_tops = ops_per_product * products / (ms / 1e3) / 1e12
@@ -193,6 +212,7 @@ def main():
                    "q_bits": 30, "limbs": limbs, "tile_t": pm.polymul_tune_get(n, limbs), "tune_cache": tuned},
         "roofline": {"bound": "mfma", "achieved": achieved_tops, "peak": PEAK_INT8_TOPS, "unit": "TFLOP/s",
                      "frac": achieved_tops / PEAK_INT8_TOPS, "traffic": measured_traffic(), "kernel": KERNEL},
+        "karatsuba": kara,
         "plain_int": {"value": plain_value, "unit": "polymuls/s", "ms_per_step": ms_plain,
                       "mfma_speedup": value / plain_value},
     }
