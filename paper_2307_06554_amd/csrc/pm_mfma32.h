@@ -221,16 +221,21 @@ __device__ __forceinline__ void a_align(v4i (&a)[L], const uint32_t (&x)[L][5], 
 }
 // One K-step of L*L MFMAs, B limb (column) by column.  As soon as column j is
 // issued, b[j] takes the next step's read for limb j, which then has the rest
-// of this step to land.
+// of this step to land.  The reads are unconditional (the caller clamps the
+// address on the last step) so that the loop body has no branches and keeps
+// its registers in place.
 template <int L>
 __device__ __forceinline__ void mfma_step(v16i (&acc)[2 * L - 1], const v4i (&a)[L], v4i (&b)[L],
-                                          const uint8_t* bplane, uint32_t b_plane, int boff_next, bool next) {
+                                          const uint8_t* bplane, uint32_t b_plane, int boff_next) {
 #pragma unroll
   for (int j = 0; j < L; ++j) {
 #pragma unroll
     for (int i = 0; i < L; ++i)
       acc[i + j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], b[j], acc[i + j], 0, 0, 0);
-    if (next) b[j] = *(const v4i*)(bplane + j * b_plane + boff_next);
+    b[j] = *(const v4i*)(bplane + j * b_plane + boff_next);
+    // keep each refill right behind its column: the scheduler would otherwise sink it
+    // to the next step's first use and expose the LDS latency
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
@@ -262,11 +267,11 @@ __device__ __forceinline__ void mfma32_tile(const Mfma32Params& P, const uint8_t
   araw_load<L>(araw, aplane, a_plane, S);
   b_load<L>(b, bplane, b_plane, B_of(0));
   for (int st = 0; st < steps; ++st) {
-    const bool next = st + 1 < steps;  // uniform
     a_align<L>(af, araw, (uint32_t)(S & 3));
-    S = S_of(st + 1);
-    if (next) araw_load<L>(araw, aplane, a_plane, S);
-    mfma_step<L>(acc, af, b, bplane, b_plane, B_of(st + 1), next);
+    const int sn = st + 1 < steps ? st + 1 : st;  // the last step re-reads its own (in-bounds) runs
+    S = S_of(sn);
+    araw_load<L>(araw, aplane, a_plane, S);
+    mfma_step<L>(acc, af, b, bplane, b_plane, B_of(sn));
   }
 }
 

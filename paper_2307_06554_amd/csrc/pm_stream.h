@@ -330,11 +330,11 @@ __device__ __forceinline__ void stream_block(const StreamParams& P, uint64_t wg,
       araw_load<L>(araw, abuf, P.a_win, S);
       b_load<L>(b, ring, kRing * P.rs, B_of(0));
       for (int st = 0; st < steps; ++st) {
-        const bool next = st + 1 < steps;
         a_align<L>(af, araw, (uint32_t)(S & 3));
-        S = S_of(st + 1);
-        if (next) araw_load<L>(araw, abuf, P.a_win, S);
-        mfma_step<L>(acc, af, b, ring, kRing * P.rs, B_of(st + 1), next);
+        const int sn = st + 1 < steps ? st + 1 : st;  // the last step re-reads its own runs
+        S = S_of(sn);
+        araw_load<L>(araw, abuf, P.a_win, S);
+        mfma_step<L>(acc, af, b, ring, kRing * P.rs, B_of(sn));
       }
       if (!more || (c + 1) % (int)P.flush_every == 0) stream_flush<L, W>(acc, res, m);
     }
