@@ -239,6 +239,44 @@ __device__ __forceinline__ void mfma_step(v16i (&acc)[2 * L - 1], const v4i (&a)
   }
 }
 
+// The same K-step with the A fragments double-buffered: after column L-2 the
+// next step's runs (read one step earlier) are aligned into `an` and the runs of
+// the step after that are read, so the next step starts straight with MFMAs.
+template <int L>
+__device__ __forceinline__ void mfma_step_pp(v16i (&acc)[2 * L - 1], const v4i (&a)[L], v4i (&an)[L],
+                                             uint32_t (&araw)[L][5], uint32_t sh_next, const uint8_t* aplane,
+                                             uint32_t a_plane, int S_after, v4i (&b)[L], const uint8_t* bplane,
+                                             uint32_t b_plane, int boff_next) {
+#pragma unroll
+  for (int j = 0; j < L; ++j) {
+#pragma unroll
+    for (int i = 0; i < L; ++i)
+      acc[i + j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], b[j], acc[i + j], 0, 0, 0);
+    b[j] = *(const v4i*)(bplane + j * b_plane + boff_next);
+    if (j == (L >= 2 ? L - 2 : 0)) {
+      // limb by limb: align, then re-read the freed raw registers; interleaved
+      // with this column's MFMAs (one MFMA, four aligns, three LDS reads)
+#pragma unroll
+      for (int i = 0; i < L; ++i) {
+        an[i][0] = (int)__builtin_amdgcn_alignbyte(araw[i][1], araw[i][0], sh_next);
+        an[i][1] = (int)__builtin_amdgcn_alignbyte(araw[i][2], araw[i][1], sh_next);
+        an[i][2] = (int)__builtin_amdgcn_alignbyte(araw[i][3], araw[i][2], sh_next);
+        an[i][3] = (int)__builtin_amdgcn_alignbyte(araw[i][4], araw[i][3], sh_next);
+        const uint32_t* p = (const uint32_t*)(aplane + i * a_plane) + (S_after >> 2);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) araw[i][k] = p[k];
+      }
+#pragma unroll
+      for (int i = 0; i < L; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, 3, 0);
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
 // One 32x32 output tile of one product: the whole K loop for all L*L limb pairs.
 // Per step: byte-align the A runs read during the previous step, issue the next
 // step's A reads into the freed raw registers, then the MFMAs (which refill B).
@@ -261,18 +299,26 @@ __device__ __forceinline__ void mfma32_tile(const Mfma32Params& P, const uint8_t
   auto S_of = [&](int st) { return S0 - ((st >> P.log2spd) << P.log2t) + ((st & (P.spd - 1)) << 5); };
   auto B_of = [&](int st) { return B0 - (st >> P.log2spd) * rs + ((st & (P.spd - 1)) << 5); };
 
+  // Steps past the end are clamped to the last one: their reads stay in bounds
+  // and their results are never used.
+  auto clamp = [&](int st) { return st < steps ? st : steps - 1; };
   uint32_t araw[L][5];
-  v4i af[L], b[L];
-  int S = S_of(0);
-  araw_load<L>(araw, aplane, a_plane, S);
+  v4i a0[L], a1[L], b[L];
+  const int S_first = S_of(0);
+  araw_load<L>(araw, aplane, a_plane, S_first);
   b_load<L>(b, bplane, b_plane, B_of(0));
-  for (int st = 0; st < steps; ++st) {
-    a_align<L>(af, araw, (uint32_t)(S & 3));
-    const int sn = st + 1 < steps ? st + 1 : st;  // the last step re-reads its own (in-bounds) runs
-    S = S_of(sn);
-    araw_load<L>(araw, aplane, a_plane, S);
-    mfma_step<L>(acc, af, b, bplane, b_plane, B_of(sn));
+  a_align<L>(a0, araw, (uint32_t)(S_first & 3));
+  araw_load<L>(araw, aplane, a_plane, S_of(clamp(1)));
+  int st = 0;
+  for (; st + 1 < steps; st += 2) {
+    mfma_step_pp<L>(acc, a0, a1, araw, (uint32_t)(S_of(st + 1) & 3), aplane, a_plane, S_of(clamp(st + 2)), b,
+                    bplane, b_plane, B_of(st + 1));
+    mfma_step_pp<L>(acc, a1, a0, araw, (uint32_t)(S_of(clamp(st + 2)) & 3), aplane, a_plane,
+                    S_of(clamp(st + 3)), b, bplane, b_plane, B_of(clamp(st + 2)));
   }
+  if (st < steps)
+    mfma_step_pp<L>(acc, a0, a1, araw, (uint32_t)(S_of(st) & 3), aplane, a_plane, S_of(st), b, bplane, b_plane,
+                    B_of(st));
 }
 
 // Recombination c = sum_s T_s 2^(8s) mod q of the 16 outputs a lane holds, then
