@@ -6,8 +6,9 @@ One step = one pass of the whole path over one batch: the n = 4096 RNS workload
 q_i = 1 mod 2n, i.e. 2048 independent limb-products) through
 polymul_negacyclic_rns, inputs already resident in HBM.  Prints one JSON line
 on stdout.  The same batch also goes through the Karatsuba route
-(polymul_negacyclic_rns_karatsuba, reported beside the headline) and the plain
-integer kernel.  --all also times the other workloads (to stderr).
+(polymul_negacyclic_rns_karatsuba), the shared-operand route with one b per
+channel (polymul_negacyclic_rns_shared), both reported beside the headline, and
+the plain integer kernel.  --all also times the other workloads (to stderr).
 """
 import argparse
 import hashlib
@@ -192,6 +193,15 @@ def main():
                 "mfma_ops_per_step": sub_ops, "schoolbook_equivalent_tops": 2 * 16 * n * n * products / ms_k / 1e9}
         del ws, ck
 
+    # one b per channel shared by all 256 pairs (same shapes and work, b staged once per chunk)
+    bs = b[0].contiguous()
+    cs = torch.empty_like(a)
+    ms_s = time_steps(lambda: pm.polymul_negacyclic_rns_shared(a, bs, w.qs, out=cs), args.steps, args.warmup)
+    shared = {"value": products / (ms_s / 1e3), "unit": "polymuls/s", "ms_per_step": ms_s,
+              "speedup_vs_direct": ms / ms_s, "b": "pair 0's b for every pair, one per channel",
+              "kernel": "mfma32_shared_kernel<4>"}
+    del bs, cs
+
     limbs = 4  # int8 limbs per operand for a 30-bit modulus
     ops_per_product = 2 * limbs * limbs * n * n
     achieved_tops = ops_per_product * products / (ms / 1e3) / 1e12
@@ -213,6 +223,7 @@ def main():
         "roofline": {"bound": "mfma", "achieved": achieved_tops, "peak": PEAK_INT8_TOPS, "unit": "TFLOP/s",
                      "frac": achieved_tops / PEAK_INT8_TOPS, "traffic": measured_traffic(), "kernel": KERNEL},
         "karatsuba": kara,
+        "shared_operand": shared,
         "plain_int": {"value": plain_value, "unit": "polymuls/s", "ms_per_step": ms_plain,
                       "mfma_speedup": value / plain_value},
     }

@@ -132,6 +132,28 @@ polymul_status polymul_plan_execute(polymul_plan* plan, hipStream_t stream);
 polymul_status polymul_plan_destroy(polymul_plan* plan);
 
 /*
+ * One operand shared by the whole batch (paper Sec. 2.2: one fixed matrix
+ * times many vectors is a single matrix product; Sec. 4, fine-tuning (i): keep
+ * one operand fixed so that what was prepared for it is reused).  Computes
+ * c[i] = a[i] * b mod (x^n + 1, q) for every i: b's digit rows are staged
+ * once per workgroup and reused for a chunk of products, only a[i] is staged
+ * per product.  Same results as polymul_negacyclic with b repeated.
+ *
+ *   a, c: device, [batch][n] words (RNS: [batch][L][n], channel l mod q[l]).
+ *   b:    device, [n] words (RNS: [L][n], one b per channel).
+ *   c must not overlap a or b; a and b may overlap each other.
+ * Other arguments, alignment and errors as for polymul_negacyclic /
+ * polymul_negacyclic_rns / polymul_negacyclic_u64.
+ */
+polymul_status polymul_negacyclic_shared(const uint32_t* a, const uint32_t* b, uint32_t* c,
+                                         uint64_t n, uint32_t q, uint64_t batch, hipStream_t stream);
+polymul_status polymul_negacyclic_rns_shared(const uint32_t* a, const uint32_t* b, uint32_t* c,
+                                             uint64_t n, const uint32_t* q, uint32_t L,
+                                             uint64_t batch, hipStream_t stream);
+polymul_status polymul_negacyclic_u64_shared(const uint64_t* a, const uint64_t* b, uint64_t* c,
+                                             uint64_t n, uint64_t q, uint64_t batch, hipStream_t stream);
+
+/*
  * Karatsuba's three-for-four trade (paper Sec. 4, the Karatsuba paragraph) on
  * top of the matrix product.  The paper splits each operand into a low and a
  * high half; in Z_q[x]/(x^n+1) this library splits into even and odd halves

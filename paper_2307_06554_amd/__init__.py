@@ -15,6 +15,9 @@ from .binding import (  # noqa: F401
     polymul_negacyclic_plain,
     polymul_negacyclic_rns,
     polymul_negacyclic_rns_karatsuba,
+    polymul_negacyclic_rns_shared,
+    polymul_negacyclic_shared,
+    polymul_negacyclic_u64_shared,
     polymul_negacyclic_u64,
     polymul_plan_create,
     polymul_plan_destroy,

@@ -31,6 +31,9 @@ _SIGNATURES = {
     "polymul_cyclic": (ctypes.c_int, [_vp, _vp, _vp, _u64, _u32, _u64, _vp]),
     "polymul_cyclic_u64": (ctypes.c_int, [_vp, _vp, _vp, _u64, _u64, _u64, _vp]),
     "polymul_tune_set": (ctypes.c_int, [_u64, _u32, _u32]),
+    "polymul_negacyclic_shared": (ctypes.c_int, [_vp, _vp, _vp, _u64, _u32, _u64, _vp]),
+    "polymul_negacyclic_rns_shared": (ctypes.c_int, [_vp, _vp, _vp, _u64, _vp, _u32, _u64, _vp]),
+    "polymul_negacyclic_u64_shared": (ctypes.c_int, [_vp, _vp, _vp, _u64, _u64, _u64, _vp]),
     "polymul_karatsuba_workspace_size": (ctypes.c_int, [_u64, _u32, _u64, _u32, ctypes.POINTER(_u64)]),
     "polymul_negacyclic_rns_karatsuba": (ctypes.c_int, [_vp, _vp, _vp, _u64, _vp, _u32, _u64, _u32, _vp, _u64,
                                                         _vp]),
@@ -179,6 +182,48 @@ def polymul_negacyclic_rns(a, b, qs, out=None, stream=None):
     st = load_library().polymul_negacyclic_rns(_words(a, 4, "a"), _words(b, 4, "b"), _words(c, 4, "out"),
                                               n, ctypes.cast(qarr, ctypes.c_void_p), L, batch, _stream(stream))
     _check(st, "polymul_negacyclic_rns")
+    return c
+
+
+def _shared(name, a, b, q, out, stream, nbytes):
+    import torch
+    if a.dim() < 1 or b.dim() != 1 or b.shape[0] != a.shape[-1]:
+        raise ValueError("a must be [..., n] and b [n]")
+    n = a.shape[-1]
+    batch = a.numel() // n if n else 0
+    c = torch.empty_like(a) if out is None else out
+    if c.shape != a.shape:
+        raise ValueError("out has the wrong shape")
+    st = getattr(load_library(), name)(_words(a, nbytes, "a"), _words(b, nbytes, "b"), _words(c, nbytes, "out"),
+                                       n, int(q), batch, _stream(stream))
+    _check(st, name)
+    return c
+
+
+def polymul_negacyclic_shared(a, b, q, out=None, stream=None):
+    """c[i] = a[i] * b in Z_q[x]/(x^n+1): a is [..., n], b one [n] polynomial (32-bit words)."""
+    return _shared("polymul_negacyclic_shared", a, b, q, out, stream, 4)
+
+
+def polymul_negacyclic_u64_shared(a, b, q, out=None, stream=None):
+    """As polymul_negacyclic_shared for 64-bit words, q < 2^64."""
+    return _shared("polymul_negacyclic_u64_shared", a, b, q, out, stream, 8)
+
+
+def polymul_negacyclic_rns_shared(a, b, qs, out=None, stream=None):
+    """RNS form with one b per channel: a is [batch, L, n], b is [L, n]."""
+    import torch
+    if a.dim() != 3 or b.dim() != 2 or b.shape != a.shape[1:]:
+        raise ValueError("a must be [batch, L, n] and b [L, n]")
+    batch, L, n = a.shape
+    if len(qs) != L:
+        raise ValueError("need one modulus per channel")
+    c = torch.empty_like(a) if out is None else out
+    qarr = (ctypes.c_uint32 * L)(*[int(x) for x in qs])
+    st = load_library().polymul_negacyclic_rns_shared(_words(a, 4, "a"), _words(b, 4, "b"), _words(c, 4, "out"),
+                                                     n, ctypes.cast(qarr, ctypes.c_void_p), L, batch,
+                                                     _stream(stream))
+    _check(st, "polymul_negacyclic_rns_shared")
     return c
 
 

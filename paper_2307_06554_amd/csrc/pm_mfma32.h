@@ -52,6 +52,7 @@ struct Mfma32Params {
   uint32_t lc, nq_total, l0, lrep;
   uint32_t fast_epilogue;  // 1: sum_s T_s * rcent[s] is known to stay below 2^62 in magnitude
   uint32_t cyclic;         // 1: ring Z_q[x]/(x^n - 1): wrapped terms keep their sign
+  uint32_t b_shared;       // 1: one b per modulus channel, b + (l0 + channel) * n, for every product
   ModQ32 mods[kMaxQ];
   int32_t rcent[kMaxQ][8];  // 2^(8s) mod q as a centred residue, s < 2L-1
 };
@@ -73,10 +74,10 @@ __device__ __forceinline__ void transpose_store(uint8_t* base, uint32_t plane, u
 //   B: rows v in [v_lo, v_lo + b_rows): row v < r holds b[v t + w] for v >= 0 and
 //      -b[(v + r) t + w] for v < 0; rows v >= r and bytes w >= t are zero.
 template <int L>
-__device__ __forceinline__ void mfma32_stage(const Mfma32Params& P, uint8_t* slot, uint64_t gprod,
+__device__ __forceinline__ void mfma32_stage(const Mfma32Params& P, uint8_t* slot, uint64_t gprod, uint64_t bprod,
                                              const ModQ32& m, int v_lo) {
   const uint32_t* A = P.a + gprod * P.n;
-  const uint32_t* B = P.b + gprod * P.n;
+  const uint32_t* B = P.b + bprod * P.n;
   const uint32_t q = m.q, thr = m.thr;
   const int n = (int)P.n, t = (int)P.t, r = (int)P.r;
   const int a_dw = (int)(P.a_plane >> 2);
@@ -281,12 +282,10 @@ __device__ __forceinline__ void mfma_step_pp(v16i (&acc)[2 * L - 1], const v4i (
 // Per step: byte-align the A runs read during the previous step, issue the next
 // step's A reads into the freed raw registers, then the MFMAs (which refill B).
 template <int L>
-__device__ __forceinline__ void mfma32_tile(const Mfma32Params& P, const uint8_t* slot, int z0, int u0,
-                                            int v_lo, v16i (&acc)[2 * L - 1]) {
+__device__ __forceinline__ void mfma32_tile(const Mfma32Params& P, const uint8_t* aplane, const uint8_t* bplane,
+                                            int z0, int u0, int v_lo, v16i (&acc)[2 * L - 1]) {
   const int lane = threadIdx.x & 63;
   const int zl = lane & 31, g = lane >> 5;
-  const uint8_t* aplane = slot;
-  const uint8_t* bplane = slot + L * P.a_plane;
   // A: lane reads reversed positions S .. S+15 with S = E - (d t + z - w0 - 16 g).
   const int S0 = (int)P.E - (z0 + zl) + 16 * g;
   // B: lane reads row (u - d) - v_lo, bytes w0 + 16 g .. + 15.
@@ -386,6 +385,11 @@ __device__ __forceinline__ uint64_t global_product(const Mfma32Params& P, uint64
   return (prod / P.lc) * P.nq_total + P.l0 + *li;
 }
 
+// Product whose b a staged product uses: its own, or its channel's shared one.
+__device__ __forceinline__ uint64_t b_product(const Mfma32Params& P, uint64_t gp, uint32_t li) {
+  return P.b_shared ? (uint64_t)(P.l0 + li) : gp;
+}
+
 // Slot-indexed fields by selects (a dynamic index would put the arrays in scratch).
 __device__ __forceinline__ uint64_t slot_gp(const GroupInfo& g, uint32_t s) {
   return s == 0 ? g.gp[0] : s == 1 ? g.gp[1] : s == 2 ? g.gp[2] : g.gp[3];
@@ -419,7 +423,48 @@ __device__ __forceinline__ const uint4* item_src(const Mfma32Params& P, const Gr
   if (s >= gi.nslots) return nullptr;
   const uint64_t gp = slot_gp(gi, s);
   if (j < quarter) return (const uint4*)(P.a + gp * P.n) + j;
-  return (const uint4*)(P.b + gp * P.n) + (j - quarter);
+  return (const uint4*)(P.b + b_product(P, gp, slot_li(gi, s)) * P.n) + (j - quarter);
+}
+
+// Word group a[4j .. 4j+3] into the reversed ext planes at abase: dword
+// (E+1)/4 - 1 - j, byte k holding ext[4j + 3 - k], and its negated copy n/4
+// dwords further when that lands inside the window.
+template <int L>
+__device__ __forceinline__ void stage_a_item(const Mfma32Params& P, uint8_t* abase, uint32_t j, uint4 x,
+                                             const ModQ32& m) {
+  const uint32_t q = m.q, thr = m.thr, quarter = P.n >> 2;
+  const uint32_t xr[4] = {reduce_u32(x.w, m), reduce_u32(x.z, m), reduce_u32(x.y, m), reduce_u32(x.x, m)};
+  uint32_t w[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) w[k] = digits32<L>(xr[k], q, thr);
+  const uint32_t dw = ((P.E + 1) >> 2) - 1 - j;
+  transpose_store<L>(abase, P.a_plane, dw * 4, w);
+  const uint32_t dwn = dw + quarter;
+  if (dwn < (P.a_plane >> 2)) {
+    uint32_t nw[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) nw[k] = P.cyclic ? w[k] : neg_digits32<L>(xr[k], q, thr);
+    transpose_store<L>(abase, P.a_plane, dwn * 4, nw);
+  }
+}
+
+// Word group e of b (row vs = e / (t/4), words 4wd..) into the staged B rows at
+// bbase: row vs (+) and row vs - r (-), relative to v_lo, where they are staged.
+template <int L>
+__device__ __forceinline__ void stage_b_item(const Mfma32Params& P, uint8_t* bbase, int v_lo, uint32_t e, uint4 x,
+                                             const ModQ32& m) {
+  const uint32_t q = m.q, thr = m.thr;
+  const uint32_t xr[4] = {reduce_u32(x.x, m), reduce_u32(x.y, m), reduce_u32(x.z, m), reduce_u32(x.w, m)};
+  const int vs = (int)(e >> (P.log2t - 2)), wd = (int)(e & ((P.t >> 2) - 1));
+  uint32_t w[4], nw[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    w[k] = digits32<L>(xr[k], q, thr);
+    nw[k] = P.cyclic ? w[k] : neg_digits32<L>(xr[k], q, thr);
+  }
+  const int rp = vs - v_lo, rn = vs - (int)P.r - v_lo;
+  if (rp >= 0 && rp < (int)P.b_rows) transpose_store<L>(bbase, P.b_plane, rp * P.b_rowstride + wd * 4, w);
+  if (rn >= 0 && rn < (int)P.b_rows) transpose_store<L>(bbase, P.b_plane, rn * P.b_rowstride + wd * 4, nw);
 }
 
 template <int L>
@@ -428,46 +473,20 @@ __device__ __forceinline__ void item_store(const Mfma32Params& P, const GroupInf
   const uint32_t lper = P.log2n - 1, quarter = P.n >> 2;
   const uint32_t s = i >> lper, j = i & ((1u << lper) - 1);
   const ModQ32& m = P.mods[slot_li(gi, s)];
-  const uint32_t q = m.q, thr = m.thr;
   uint8_t* slot = smem + s * P.slot_bytes;
-  const uint32_t xr[4] = {reduce_u32(x.x, m), reduce_u32(x.y, m), reduce_u32(x.z, m), reduce_u32(x.w, m)};
-  uint32_t w[4], nw[4];
-  if (j < quarter) {
-    // reversed: byte k of dword (E+1)/4 - 1 - j holds ext[4j + 3 - k]
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      w[k] = digits32<L>(xr[3 - k], q, thr);
-      nw[k] = P.cyclic ? w[k] : neg_digits32<L>(xr[3 - k], q, thr);
-    }
-    const uint32_t dw = ((P.E + 1) >> 2) - 1 - j;
-    transpose_store<L>(slot, P.a_plane, dw * 4, w);
-    const uint32_t dwn = dw + quarter;
-    if (dwn < (P.a_plane >> 2)) transpose_store<L>(slot, P.a_plane, dwn * 4, nw);
-  } else {
-    const uint32_t e = j - quarter;
-    const int vs = (int)(e >> (P.log2t - 2)), wd = (int)(e & ((P.t >> 2) - 1));
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      w[k] = digits32<L>(xr[k], q, thr);
-      nw[k] = P.cyclic ? w[k] : neg_digits32<L>(xr[k], q, thr);
-    }
-    uint8_t* bbase = slot + L * P.a_plane;
-    const int rp = vs - gi.v_lo, rn = vs - (int)P.r - gi.v_lo;
-    if (rp >= 0 && rp < (int)P.b_rows) transpose_store<L>(bbase, P.b_plane, rp * P.b_rowstride + wd * 4, w);
-    if (rn >= 0 && rn < (int)P.b_rows) transpose_store<L>(bbase, P.b_plane, rn * P.b_rowstride + wd * 4, nw);
-  }
+  if (j < quarter) stage_a_item<L>(P, slot, j, x, m);
+  else stage_b_item<L>(P, slot + L * P.a_plane, gi.v_lo, j - quarter, x, m);
 }
 
 // Parts of the staged B rows that no item writes but valid outputs read: bytes
 // w in [t, rowlen) of rows v < r (only when t < 32).  Rows v >= r feed only
 // discarded output columns; they are cleared too so LDS content is deterministic.
 template <int L>
-__device__ __forceinline__ void stage_zero_fill(const Mfma32Params& P, const GroupInfo& gi, uint8_t* smem) {
+__device__ __forceinline__ void zero_fill_b(const Mfma32Params& P, uint8_t* bbase, int v_lo) {
   const int row_dw = (int)(P.rowlen >> 2);
   const int tq = (int)(P.t >> 2);
-  const int zr0 = max(0, (int)P.r - gi.v_lo);  // first row with v >= r
-  for (uint32_t s = 0; s < gi.nslots; ++s) {
-    uint8_t* bbase = smem + s * P.slot_bytes + L * P.a_plane;
+  const int zr0 = max(0, (int)P.r - v_lo);  // first row with v >= r
+  {
     if (tq < row_dw) {
       const int pad = row_dw - tq;
       const int cnt = zr0 < (int)P.b_rows ? zr0 * pad : (int)P.b_rows * pad;
@@ -485,6 +504,10 @@ __device__ __forceinline__ void stage_zero_fill(const Mfma32Params& P, const Gro
     }
   }
 }
+template <int L>
+__device__ __forceinline__ void stage_zero_fill(const Mfma32Params& P, const GroupInfo& gi, uint8_t* smem) {
+  for (uint32_t s = 0; s < gi.nslots; ++s) zero_fill_b<L>(P, smem + s * P.slot_bytes + L * P.a_plane, gi.v_lo);
+}
 
 // One group of four 32x32 tiles: stage the products it touches, then each wave
 // runs its tile.  SMALL: n < 4, staged byte by byte.  Ends with every wave
@@ -496,7 +519,8 @@ __device__ __forceinline__ void resident_group(const Mfma32Params& P, uint64_t g
   const GroupInfo gi = group_info(P, grp);
   if constexpr (SMALL) {
     for (uint32_t s = 0; s < gi.nslots; ++s)
-      mfma32_stage<L>(P, smem + s * P.slot_bytes, slot_gp(gi, s), P.mods[slot_li(gi, s)], gi.v_lo);
+      mfma32_stage<L>(P, smem + s * P.slot_bytes, slot_gp(gi, s), b_product(P, slot_gp(gi, s), slot_li(gi, s)),
+                      P.mods[slot_li(gi, s)], gi.v_lo);
   } else {
     // all loads of a pass are issued before any is converted
     const uint32_t nitems = gi.nslots * (P.n >> 1);
@@ -526,7 +550,7 @@ __device__ __forceinline__ void resident_group(const Mfma32Params& P, uint64_t g
   const uint8_t* slot = smem + sl * P.slot_bytes;
   const int v_lo = gi.v_lo;
   v16i acc[2 * L - 1];
-  mfma32_tile<L>(P, slot, 32 * zt, 32 * ut, v_lo, acc);
+  mfma32_tile<L>(P, slot, slot + L * P.a_plane, 32 * zt, 32 * ut, v_lo, acc);
   uint32_t li;
   const uint64_t gprod = global_product(P, prod, &li);
   mfma32_epilogue<L>(P, gprod, P.mods[li], P.rcent[li], 32 * zt, 32 * ut, acc);
@@ -538,6 +562,102 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
 void mfma32_group_kernel(const Mfma32Params P) {
   extern __shared__ __align__(16) uint8_t smem[];
   resident_group<L, SMALL>(P, blockIdx.x, smem);
+}
+
+// ---------------------------------------------------------------------------
+// One b shared by a whole batch (paper Sec. 4, fine-tuning (i): keep one operand
+// fixed and reuse what was prepared for it).  A workgroup takes a chunk of
+// consecutive groups of one modulus channel and one tile position; b's digit
+// rows are staged once per chunk, each group then stages only a.  LDS layout:
+// [L planes of B rows][slots x L planes of A].
+// ---------------------------------------------------------------------------
+struct SharedChunks {
+  uint64_t batch;             // products per channel
+  uint32_t npos;              // tile positions per product: max(1, U / 4)
+  uint32_t groups_per_class;  // U >= 4: batch; else ceil(batch / slots)
+  uint32_t chunk;             // groups per workgroup
+  uint32_t chunks_per_class;  // ceil(groups_per_class / chunk)
+};
+
+template <int L>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void mfma32_shared_kernel(const Mfma32Params P, const SharedChunks C) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const uint32_t cls = blockIdx.x / C.chunks_per_class;
+  const uint32_t part = blockIdx.x - cls * C.chunks_per_class;
+  const uint32_t l = cls / C.npos, pos = cls - l * C.npos;
+  const uint32_t U = 1u << P.log2U;
+  const int ut_lo = U >= 4 ? (int)((pos * 4) / P.tz) : 0;
+  const int v_lo = 32 * ut_lo - ((int)P.r - 1);
+  const ModQ32& m = P.mods[l];
+  uint8_t* bbase = smem;
+  uint8_t* abase = smem + L * P.b_plane;
+  const uint32_t a_slot = L * P.a_plane;
+  const uint32_t quarter = P.n >> 2;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+
+  // b's rows for this channel and tile position, once per chunk
+  {
+    const uint4* src = (const uint4*)(P.b + (uint64_t)(P.l0 + l) * P.n);
+    for (uint32_t base = 0; base < quarter; base += kPrefetch * kThreads) {
+      uint4 pf[kPrefetch];
+#pragma unroll
+      for (int k = 0; k < kPrefetch; ++k) {
+        const uint32_t e = base + threadIdx.x + k * kThreads;
+        pf[k] = e < quarter ? src[e] : make_uint4(0, 0, 0, 0);
+      }
+#pragma unroll
+      for (int k = 0; k < kPrefetch; ++k) {
+        const uint32_t e = base + threadIdx.x + k * kThreads;
+        if (e < quarter) stage_b_item<L>(P, bbase, v_lo, e, pf[k], m);
+      }
+    }
+    zero_fill_b<L>(P, bbase, v_lo);
+  }
+
+  const uint32_t g0 = part * C.chunk;
+  const uint32_t g1 = min(g0 + C.chunk, C.groups_per_class);
+  for (uint32_t g = g0; g < g1; ++g) {
+    // batch indices of this group's products and how many exist
+    const uint64_t i0 = U >= 4 ? (uint64_t)g : (uint64_t)g * P.slots;
+    const uint32_t nsl = U >= 4 ? 1u : (uint32_t)min((uint64_t)P.slots, C.batch - i0);
+    const uint32_t nitems = nsl * quarter;  // a's word groups
+    for (uint32_t base = 0; base < nitems; base += kPrefetch * kThreads) {
+      uint4 pf[kPrefetch];
+#pragma unroll
+      for (int k = 0; k < kPrefetch; ++k) {
+        const uint32_t i = base + threadIdx.x + k * kThreads;
+        pf[k] = make_uint4(0, 0, 0, 0);
+        if (i < nitems) {
+          const uint32_t sl = i >> (P.log2n - 2), j = i & (quarter - 1);
+          uint32_t li;
+          const uint64_t gp = global_product(P, (i0 + sl) * P.lc + l, &li);
+          pf[k] = ((const uint4*)(P.a + gp * P.n))[j];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < kPrefetch; ++k) {
+        const uint32_t i = base + threadIdx.x + k * kThreads;
+        if (i < nitems) {
+          const uint32_t sl = i >> (P.log2n - 2), j = i & (quarter - 1);
+          stage_a_item<L>(P, abase + sl * a_slot, j, pf[k], m);
+        }
+      }
+    }
+    __syncthreads();
+    // wave -> (slot, tile)
+    const uint32_t sl = U >= 4 ? 0u : wave >> P.log2U;
+    const uint32_t tile = U >= 4 ? pos * 4 + wave : (wave & (U - 1));
+    if (sl < nsl) {
+      const int zt = (int)(tile % P.tz), ut = (int)(tile / P.tz);
+      v16i acc[2 * L - 1];
+      mfma32_tile<L>(P, abase + sl * a_slot, bbase, 32 * zt, 32 * ut, v_lo, acc);
+      uint32_t li;
+      const uint64_t gp = global_product(P, (i0 + sl) * P.lc + l, &li);
+      mfma32_epilogue<L>(P, gp, m, P.rcent[l], 32 * zt, 32 * ut, acc);
+    }
+    __syncthreads();  // a's planes are restaged for the next group
+  }
 }
 
 }  // namespace pm

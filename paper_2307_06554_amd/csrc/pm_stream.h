@@ -43,6 +43,7 @@ struct StreamParams {
   uint32_t lds_b;         // LDS offset of the B ring
   uint32_t lc, nq_total, l0;  // product i -> global (i/lc)*nq_total + l0 + i%lc, modulus i%lc
   uint32_t lrep;              // > 1: product i is global i with modulus (i/lrep)%lc
+  uint32_t b_shared;          // 1: one b per channel, b + (l0 + channel) * n, for every product
   uint32_t cyclic;            // 1: ring Z_q[x]/(x^n - 1): wrapped terms keep their sign
   ModQ64 mods[kMaxQS];
 };
@@ -148,7 +149,8 @@ __device__ __forceinline__ ChunkItems chunk_items(const StreamParams& P, int c, 
 
 // Global source of an item (nullptr: the item is all zeros).
 template <typename W>
-__device__ __forceinline__ const W* item_ptr(const StreamParams& P, const StreamItem& it, uint64_t gp, bool* neg) {
+__device__ __forceinline__ const W* item_ptr(const StreamParams& P, const StreamItem& it, uint64_t gp, uint64_t bgp,
+                                             bool* neg) {
   const int n = (int)P.n, t = (int)P.t, r = (int)P.r;
   *neg = false;
   if (it.kind == 1) {
@@ -161,8 +163,8 @@ __device__ __forceinline__ const W* item_ptr(const StreamParams& P, const Stream
   if (it.kind == 2) {
     const int v = it.e, w = 4 * it.k;
     if (t < 4 || w >= t) return nullptr;
-    if (v >= 0 && v < r) return (const W*)P.b + gp * P.n + (size_t)v * t + w;
-    if (v < 0 && v > -r) { *neg = !P.cyclic; return (const W*)P.b + gp * P.n + (size_t)(v + r) * t + w; }
+    if (v >= 0 && v < r) return (const W*)P.b + bgp * P.n + (size_t)v * t + w;
+    if (v < 0 && v > -r) { *neg = !P.cyclic; return (const W*)P.b + bgp * P.n + (size_t)(v + r) * t + w; }
   }
   return nullptr;
 }
@@ -170,8 +172,8 @@ __device__ __forceinline__ const W* item_ptr(const StreamParams& P, const Stream
 // Convert one item (its four words already loaded, or element-wise for tiny n) and write it.
 template <int L, typename W>
 __device__ __forceinline__ void item_write(const StreamParams& P, const StreamItem& it, const Quad<W>& x, bool live,
-                                           bool neg, uint64_t gp, const ModQ64& m, uint8_t* abuf, uint8_t* ring,
-                                           int I1) {
+                                           bool neg, uint64_t gp, uint64_t bgp, const ModQ64& m, uint8_t* abuf,
+                                           uint8_t* ring, int I1) {
   uint64_t d[4] = {0, 0, 0, 0};
   const int n = (int)P.n, t = (int)P.t, r = (int)P.r;
   if (it.kind == 1) {
@@ -203,9 +205,9 @@ __device__ __forceinline__ void item_write(const StreamParams& P, const StreamIt
       for (int k = 0; k < 4; ++k) {
         const int ww = w + k;
         if (ww >= t) continue;
-        if (v >= 0 && v < r) d[k] = digits64<L>(word_reduce<W>(((const W*)P.b)[gp * P.n + (size_t)v * t + ww], m), m);
+        if (v >= 0 && v < r) d[k] = digits64<L>(word_reduce<W>(((const W*)P.b)[bgp * P.n + (size_t)v * t + ww], m), m);
         else if (v < 0 && v > -r) {
-          const uint64_t xr = word_reduce<W>(((const W*)P.b)[gp * P.n + (size_t)(v + r) * t + ww], m);
+          const uint64_t xr = word_reduce<W>(((const W*)P.b)[bgp * P.n + (size_t)(v + r) * t + ww], m);
           d[k] = P.cyclic ? digits64<L>(xr, m) : neg_digits64<L>(xr, m);
         }
       }
@@ -255,6 +257,7 @@ __device__ __forceinline__ void stream_block(const StreamParams& P, uint64_t wg,
   const int U0 = 64 * (int)(wg - prod * P.ublocks);
   const uint32_t li = P.lrep > 1 ? (uint32_t)((prod / P.lrep) % P.lc) : (uint32_t)(prod % P.lc);
   const uint64_t gp = P.lrep > 1 ? prod : (prod / P.lc) * P.nq_total + P.l0 + li;
+  const uint64_t bgp = P.b_shared ? (uint64_t)(P.l0 + li) : gp;
   const ModQ64& m = P.mods[li];
   uint8_t* ring = smem + P.lds_b;
   const int wave = (int)(threadIdx.x >> 6);
@@ -272,10 +275,10 @@ __device__ __forceinline__ void stream_block(const StreamParams& P, uint64_t wg,
     for (int i = threadIdx.x; i < ci.count(); i += kStreamThreads) {
       const StreamItem it = ci.item(i);
       bool neg;
-      const W* src = item_ptr<W>(P, it, gp, &neg);
+      const W* src = item_ptr<W>(P, it, gp, bgp, &neg);
       Quad<W> x{};
       if (src) x = load_quad<W>(src);
-      item_write<L, W>(P, it, x, src != nullptr, neg, gp, m, smem, ring, I1);
+      item_write<L, W>(P, it, x, src != nullptr, neg, gp, bgp, m, smem, ring, I1);
     }
   }
   __syncthreads();
@@ -307,7 +310,7 @@ __device__ __forceinline__ void stream_block(const StreamParams& P, uint64_t wg,
         pn[k] = false;
         if (i < cn.count()) {
           const StreamItem it = cn.item(i);
-          const W* src = item_ptr<W>(P, it, gp, &pn[k]);
+          const W* src = item_ptr<W>(P, it, gp, bgp, &pn[k]);
           if (src) { pf[k] = load_quad<W>(src); pl[k] = true; }
         }
       }
@@ -346,15 +349,15 @@ __device__ __forceinline__ void stream_block(const StreamParams& P, uint64_t wg,
 #pragma unroll
       for (int k = 0; k < kItems; ++k) {
         const int i = (int)threadIdx.x + k * kStreamThreads;
-        if (i < cn.count()) item_write<L, W>(P, cn.item(i), pf[k], pl[k], pn[k], gp, m, abuf_n, ring, I1n);
+        if (i < cn.count()) item_write<L, W>(P, cn.item(i), pf[k], pl[k], pn[k], gp, bgp, m, abuf_n, ring, I1n);
       }
       for (int i = (int)threadIdx.x + kItems * kStreamThreads; i < cn.count(); i += kStreamThreads) {
         const StreamItem it = cn.item(i);
         bool neg;
-        const W* src = item_ptr<W>(P, it, gp, &neg);
+        const W* src = item_ptr<W>(P, it, gp, bgp, &neg);
         Quad<W> x{};
         if (src) x = load_quad<W>(src);
-        item_write<L, W>(P, it, x, src != nullptr, neg, gp, m, abuf_n, ring, I1n);
+        item_write<L, W>(P, it, x, src != nullptr, neg, gp, bgp, m, abuf_n, ring, I1n);
       }
     }
     __syncthreads();

@@ -52,6 +52,20 @@ polymul_status check_arrays(const void* a, const void* b, const void* c, uint64_
   return POLYMUL_OK;
 }
 
+// Checks for the shared-operand layout: a and c are [batch][channels][n], b is [channels][n].
+polymul_status check_shared(const void* a, const void* b, const void* c, uint64_t n, uint64_t batch,
+                            uint64_t channels, uint32_t elem) {
+  if (!is_pow2(n) || n > 65536) return POLYMUL_EINVAL;
+  if (batch == 0) return POLYMUL_OK;
+  if (!a || !b || !c) return POLYMUL_EINVAL;
+  if (((uintptr_t)a | (uintptr_t)b | (uintptr_t)c) & 15) return POLYMUL_EINVAL;
+  const unsigned __int128 big = (unsigned __int128)batch * channels * n * elem;
+  if (big >> 62) return POLYMUL_EINVAL;
+  const uint64_t bytes = (uint64_t)big, bbytes = channels * n * elem;
+  if (overlaps(c, bytes, a, bytes) || overlaps(c, bytes, b, bbytes)) return POLYMUL_EALIAS;
+  return POLYMUL_OK;
+}
+
 // POLYMUL_LOG=1 in the environment prints failing HIP calls to stderr.
 bool log_enabled() {
   static const bool on = [] {
@@ -145,7 +159,8 @@ int limbs32(const uint32_t* qs, uint32_t lc) {
 // Resident-kernel parameters; *lds gets the dynamic LDS bytes per workgroup.
 polymul_status fill_mfma32(Mfma32Params& P, const uint32_t* a, const uint32_t* b, uint32_t* c, uint32_t n,
                            const uint32_t* qs, uint32_t lc, uint32_t nq_total, uint32_t l0, uint64_t nprod, int L,
-                           uint32_t t, uint32_t* lds, bool cyclic = false, uint32_t lrep = 1) {
+                           uint32_t t, uint32_t* lds, bool cyclic = false, uint32_t lrep = 1,
+                           bool b_shared = false) {
   if (!tile_ok(n, t)) return POLYMUL_EINVAL;
   const Geometry32 g = geometry32(n, t);
   P = Mfma32Params{};
@@ -181,6 +196,7 @@ polymul_status fill_mfma32(Mfma32Params& P, const uint32_t* a, const uint32_t* b
   }
   P.fast_epilogue = fast ? 1u : 0u;
   P.cyclic = cyclic ? 1u : 0u;
+  P.b_shared = b_shared ? 1u : 0u;
   *lds = P.slots * P.slot_bytes;
   return *lds <= kMaxLds ? POLYMUL_OK : POLYMUL_EUNSUPPORTED;
 }
@@ -197,6 +213,7 @@ polymul_status allow_lds() {
 template <int L, bool SMALL> const void* k_group() { return (const void*)mfma32_group_kernel<L, SMALL>; }
 template <int L, typename W, int WPE> const void* k_stream() { return (const void*)stream_kernel<L, W, WPE>; }
 const void* k_grouped() { return (const void*)grouped_kernel<4>; }
+template <int L> const void* k_shared() { return (const void*)mfma32_shared_kernel<L>; }
 
 template <int L, bool SMALL>
 polymul_status launch_mfma32_L(const Mfma32Params& P, uint32_t lds, hipStream_t s) {
@@ -205,6 +222,43 @@ polymul_status launch_mfma32_L(const Mfma32Params& P, uint32_t lds, hipStream_t 
   if (groups > 0x7FFFFFFFull) return POLYMUL_EUNSUPPORTED;
   hipLaunchKernelGGL((mfma32_group_kernel<L, SMALL>), dim3((uint32_t)groups), dim3(kThreads), lds, s, P);
   return launch_status();
+}
+
+// One b per channel for the whole batch: workgroups take chunks of groups of one
+// channel and tile position and stage that b once.
+template <int L>
+polymul_status launch_shared_L(const Mfma32Params& P, const SharedChunks& C, uint32_t grid, uint32_t lds,
+                               hipStream_t s) {
+  if (allow_lds<k_shared<L>>() != POLYMUL_OK) return POLYMUL_EDEVICE;
+  hipLaunchKernelGGL((mfma32_shared_kernel<L>), dim3(grid), dim3(kThreads), lds, s, P, C);
+  return launch_status();
+}
+
+polymul_status launch_shared(const Mfma32Params& P, int L, uint64_t batch, hipStream_t s) {
+  const uint32_t U = 1u << P.log2U;
+  SharedChunks C{};
+  C.batch = batch;
+  C.npos = U >= 4 ? U / 4 : 1;
+  const uint64_t gpc = U >= 4 ? batch : (batch + P.slots - 1) / P.slots;
+  if (gpc > 0xFFFFFFFFull) return POLYMUL_EUNSUPPORTED;
+  C.groups_per_class = (uint32_t)gpc;
+  const uint64_t classes = (uint64_t)P.lc * C.npos;
+  const uint64_t total = classes * gpc;
+  const uint64_t target = 2ull * device_cus();  // one round of two workgroups per CU
+  uint64_t chunk = (total + target - 1) / target;
+  if (chunk < 1) chunk = 1;
+  if (chunk > gpc) chunk = gpc;
+  C.chunk = (uint32_t)chunk;
+  C.chunks_per_class = (uint32_t)((gpc + chunk - 1) / chunk);
+  const uint64_t grid = classes * C.chunks_per_class;
+  if (grid > 0x7FFFFFFFull) return POLYMUL_EUNSUPPORTED;
+  const uint64_t lds = (uint64_t)L * P.b_plane + (uint64_t)P.slots * L * P.a_plane;
+  if (lds > kMaxLds) return POLYMUL_EUNSUPPORTED;
+  switch (L) {
+    case 2: return launch_shared_L<2>(P, C, (uint32_t)grid, (uint32_t)lds, s);
+    case 3: return launch_shared_L<3>(P, C, (uint32_t)grid, (uint32_t)lds, s);
+    default: return launch_shared_L<4>(P, C, (uint32_t)grid, (uint32_t)lds, s);
+  }
 }
 
 // --------------------------------------------------------- streaming kernel
@@ -216,7 +270,7 @@ int limbs64(const uint64_t* qs, uint32_t lc) {
 
 polymul_status fill_stream(StreamParams& P, const void* a, const void* b, void* c, uint32_t n, const uint64_t* qs,
                            uint32_t lc, uint32_t nq_total, uint32_t l0, uint64_t nprod, int L, uint32_t* lds,
-                           bool cyclic = false, uint32_t lrep = 1) {
+                           bool cyclic = false, uint32_t lrep = 1, bool b_shared = false) {
   P = StreamParams{};
   P.a = a; P.b = b; P.c = c;
   P.nprod = nprod;
@@ -239,6 +293,7 @@ polymul_status fill_stream(StreamParams& P, const void* a, const void* b, void* 
   P.lds_b = 2u * (uint32_t)L * P.a_win;
   P.lc = lc; P.nq_total = nq_total; P.l0 = l0; P.lrep = lrep;
   P.cyclic = cyclic ? 1u : 0u;
+  P.b_shared = b_shared ? 1u : 0u;
   for (uint32_t i = 0; i < lc; ++i) P.mods[i] = make_mod64(qs[i], L);
   *lds = P.lds_b + (uint32_t)L * kRing * P.rs;
   return *lds <= kMaxLds ? POLYMUL_OK : POLYMUL_EUNSUPPORTED;
@@ -257,12 +312,12 @@ polymul_status launch_stream_L(const StreamParams& P, uint32_t lds, hipStream_t 
 template <typename W>
 polymul_status run_stream(const W* a, const W* b, W* c, uint32_t n, const uint64_t* qs, uint32_t lc,
                           uint32_t nq_total, uint32_t l0, uint64_t nprod, hipStream_t s, bool cyclic = false,
-                          uint32_t lrep = 1) {
+                          uint32_t lrep = 1, bool b_shared = false) {
   const int L = limbs64(qs, lc);
   if (sizeof(W) == 4 && L > 4) return POLYMUL_EINVAL;
   StreamParams P;
   uint32_t lds;
-  polymul_status st = fill_stream(P, a, b, c, n, qs, lc, nq_total, l0, nprod, L, &lds, cyclic, lrep);
+  polymul_status st = fill_stream(P, a, b, c, n, qs, lc, nq_total, l0, nprod, L, &lds, cyclic, lrep, b_shared);
   if (st != POLYMUL_OK) return st;
   if (L == 4) return launch_stream_L<4, W, 2>(P, lds, s);
   return launch_stream_L<8, W, 1>(P, lds, s);
@@ -271,7 +326,7 @@ polymul_status run_stream(const W* a, const W* b, W* c, uint32_t n, const uint64
 // nprod products (i -> global (i/lc)*nq_total + l0 + i%lc) with moduli qs[0..lc <= kMaxQ).
 polymul_status run_mfma32(const uint32_t* a, const uint32_t* b, uint32_t* c, uint32_t n, const uint32_t* qs,
                           uint32_t lc, uint32_t nq_total, uint32_t l0, uint64_t nprod, hipStream_t s,
-                          bool cyclic = false, uint32_t lrep = 1) {
+                          bool cyclic = false, uint32_t lrep = 1, bool b_shared = false) {
   if (n > 8192) {
     if (lrep > 1) {
       if (lc > (uint32_t)kMaxQS) return POLYMUL_EUNSUPPORTED;
@@ -286,7 +341,8 @@ polymul_status run_mfma32(const uint32_t* a, const uint32_t* b, uint32_t* c, uin
     for (uint32_t c0 = 0; c0 < lc; c0 += kMaxQS) {
       const uint32_t cc = std::min(lc - c0, (uint32_t)kMaxQS);
       const uint64_t np = cc == lc ? nprod : batch * cc;
-      polymul_status st = run_stream<uint32_t>(a, b, c, n, q64 + c0, cc, nq_total, l0 + c0, np, s, cyclic);
+      polymul_status st = run_stream<uint32_t>(a, b, c, n, q64 + c0, cc, nq_total, l0 + c0, np, s, cyclic, 1,
+                                               b_shared);
       if (st != POLYMUL_OK) return st;
     }
     return POLYMUL_OK;
@@ -294,9 +350,11 @@ polymul_status run_mfma32(const uint32_t* a, const uint32_t* b, uint32_t* c, uin
   const int L = limbs32(qs, lc);
   Mfma32Params P;
   uint32_t lds;
-  polymul_status st = fill_mfma32(P, a, b, c, n, qs, lc, nq_total, l0, nprod, L, tile_for(n, L), &lds, cyclic, lrep);
+  polymul_status st =
+      fill_mfma32(P, a, b, c, n, qs, lc, nq_total, l0, nprod, L, tile_for(n, L), &lds, cyclic, lrep, b_shared);
   if (st != POLYMUL_OK) return st;
   const bool small = n < 4;
+  if (b_shared && !small && lrep == 1) return launch_shared(P, L, nprod / lc, s);
   switch (L) {
     case 2: return small ? launch_mfma32_L<2, true>(P, lds, s) : launch_mfma32_L<2, false>(P, lds, s);
     case 3: return small ? launch_mfma32_L<3, true>(P, lds, s) : launch_mfma32_L<3, false>(P, lds, s);
@@ -564,6 +622,37 @@ polymul_status polymul_cyclic_u64(const uint64_t* a, const uint64_t* b, uint64_t
   polymul_status st = check_arrays(a, b, c, n, batch, 1, 8, &bytes);
   if (st != POLYMUL_OK || batch == 0) return st;
   return run_stream<uint64_t>(a, b, c, (uint32_t)n, &q, 1, 1, 0, batch, stream, true);
+}
+
+polymul_status polymul_negacyclic_shared(const uint32_t* a, const uint32_t* b, uint32_t* c, uint64_t n,
+                                         uint32_t q, uint64_t batch, hipStream_t stream) {
+  if (q < 2) return POLYMUL_EINVAL;
+  polymul_status st = check_shared(a, b, c, n, batch, 1, 4);
+  if (st != POLYMUL_OK || batch == 0) return st;
+  return run_mfma32(a, b, c, (uint32_t)n, &q, 1, 1, 0, batch, stream, false, 1, true);
+}
+
+polymul_status polymul_negacyclic_rns_shared(const uint32_t* a, const uint32_t* b, uint32_t* c, uint64_t n,
+                                             const uint32_t* q, uint32_t L, uint64_t batch, hipStream_t stream) {
+  if (L == 0 || !q) return POLYMUL_EINVAL;
+  for (uint32_t l = 0; l < L; ++l)
+    if (q[l] < 2) return POLYMUL_EINVAL;
+  polymul_status st = check_shared(a, b, c, n, batch, L, 4);
+  if (st != POLYMUL_OK || batch == 0) return st;
+  for (uint32_t l0 = 0; l0 < L; l0 += kMaxQ) {
+    const uint32_t lc = std::min(L - l0, (uint32_t)kMaxQ);
+    st = run_mfma32(a, b, c, (uint32_t)n, q + l0, lc, L, l0, batch * lc, stream, false, 1, true);
+    if (st != POLYMUL_OK) return st;
+  }
+  return POLYMUL_OK;
+}
+
+polymul_status polymul_negacyclic_u64_shared(const uint64_t* a, const uint64_t* b, uint64_t* c, uint64_t n,
+                                             uint64_t q, uint64_t batch, hipStream_t stream) {
+  if (q < 2) return POLYMUL_EINVAL;
+  polymul_status st = check_shared(a, b, c, n, batch, 1, 8);
+  if (st != POLYMUL_OK || batch == 0) return st;
+  return run_stream<uint64_t>(a, b, c, (uint32_t)n, &q, 1, 1, 0, batch, stream, false, 1, true);
 }
 
 polymul_status polymul_karatsuba_workspace_size(uint64_t n, uint32_t L, uint64_t batch, uint32_t depth,

@@ -175,3 +175,23 @@ def test_karatsuba_arguments():
     assert call(k, A, B, C, 256, qp, 2, 1, 2, A - 16, need, None) == EALIAS    # workspace overlaps a
     assert call(k, A, B, C, 256, qp, 2, 1, 2, C + 64, need, None) == EALIAS    # workspace overlaps c
     assert call(k, None, None, None, 256, qp, 2, 0, 2, None, 0, None) == 0     # empty batch
+
+
+def test_shared_operand_arguments():
+    qs = (ctypes.c_uint32 * 2)(17, 19)
+    qp = ctypes.cast(qs, ctypes.c_void_p)
+    for name in ("polymul_negacyclic_shared", "polymul_negacyclic_u64_shared"):
+        assert call(name, A, B, C, 255, 17, 4, None) == EINVAL
+        assert call(name, A, B, C, 256, 1, 4, None) == EINVAL
+        assert call(name, None, B, C, 256, 17, 4, None) == EINVAL
+        assert call(name, A, B + 8, C, 256, 17, 4, None) == EINVAL
+        assert call(name, A, B, A + 1024, 256, 17, 4, None) == EALIAS      # c overlaps a
+        assert call(name, A, B, B - 16, 256, 17, 4, None) == EALIAS        # c overlaps b
+        assert call(name, None, None, None, 256, 17, 0, None) == 0
+    k = "polymul_negacyclic_rns_shared"
+    assert call(k, A, B, C, 256, None, 2, 4, None) == EINVAL
+    assert call(k, A, B, C, 256, qp, 0, 4, None) == EINVAL
+    bad = (ctypes.c_uint32 * 2)(17, 0)
+    assert call(k, A, B, C, 256, ctypes.cast(bad, ctypes.c_void_p), 2, 4, None) == EINVAL
+    assert call(k, A, B, B + 2 * 256 * 4 - 16, 256, qp, 2, 4, None) == EALIAS  # c overlaps the end of b
+    assert call(k, None, None, None, 256, qp, 2, 0, None) == 0
