@@ -132,6 +132,33 @@ polymul_status polymul_plan_execute(polymul_plan* plan, hipStream_t stream);
 polymul_status polymul_plan_destroy(polymul_plan* plan);
 
 /*
+ * The paper's coefficient method (Sec. 2.4 RNS, Sec. 2.6 RNS base selection,
+ * Algorithm 1): every coefficient is lifted to its centred integer in
+ * (-q/2, q/2] and represented by its residues modulo co-prime moduli of at
+ * most 8 bits, taken largest first until their product M exceeds
+ * 2 n floor(q/2)^2 (1 + 2^-16) -- twice the largest possible |negacyclic sum|,
+ * so the signed sums are recovered exactly.  Each modulus is one int8 matrix
+ * product of centred residues (int32 sums, one MFMA per modulus per K-step);
+ * the Chinese remainder theorem rebuilds each sum and reduces it mod q.  Same
+ * results as polymul_negacyclic / polymul_negacyclic_rns, word for word.
+ *
+ * Arguments, layout and errors as polymul_negacyclic / polymul_negacyclic_rns;
+ * n <= 4096 (the residue planes of both operands live in LDS), else
+ * POLYMUL_EUNSUPPORTED.
+ */
+polymul_status polymul_negacyclic_crt(const uint32_t* a, const uint32_t* b, uint32_t* c,
+                                      uint64_t n, uint32_t q, uint64_t batch, hipStream_t stream);
+polymul_status polymul_negacyclic_rns_crt(const uint32_t* a, const uint32_t* b, uint32_t* c,
+                                          uint64_t n, const uint32_t* q, uint32_t L,
+                                          uint64_t batch, hipStream_t stream);
+/*
+ * The small moduli polymul_negacyclic_crt uses for degree bound n and modulus
+ * q (Algorithm 1's ExtractModuli), largest first; `moduli` must hold 11
+ * entries.  Host only, no HIP call.  EINVAL: bad n or q, null pointers.
+ */
+polymul_status polymul_crt_moduli(uint64_t n, uint32_t q, uint32_t* moduli, uint32_t* count);
+
+/*
  * One operand shared by the whole batch (paper Sec. 2.2: one fixed matrix
  * times many vectors is a single matrix product; Sec. 4, fine-tuning (i): keep
  * one operand fixed so that what was prepared for it is reused).  Computes

@@ -8,12 +8,15 @@ from .binding import (  # noqa: F401
     PolymulError,
     lib_path,
     polymul_cyclic,
+    polymul_crt_moduli,
     polymul_cyclic_u64,
     load_library,
     polymul_karatsuba_workspace_size,
     polymul_negacyclic,
+    polymul_negacyclic_crt,
     polymul_negacyclic_plain,
     polymul_negacyclic_rns,
+    polymul_negacyclic_rns_crt,
     polymul_negacyclic_rns_karatsuba,
     polymul_negacyclic_rns_shared,
     polymul_negacyclic_shared,

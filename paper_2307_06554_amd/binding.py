@@ -31,6 +31,9 @@ _SIGNATURES = {
     "polymul_cyclic": (ctypes.c_int, [_vp, _vp, _vp, _u64, _u32, _u64, _vp]),
     "polymul_cyclic_u64": (ctypes.c_int, [_vp, _vp, _vp, _u64, _u64, _u64, _vp]),
     "polymul_tune_set": (ctypes.c_int, [_u64, _u32, _u32]),
+    "polymul_negacyclic_crt": (ctypes.c_int, [_vp, _vp, _vp, _u64, _u32, _u64, _vp]),
+    "polymul_negacyclic_rns_crt": (ctypes.c_int, [_vp, _vp, _vp, _u64, _vp, _u32, _u64, _vp]),
+    "polymul_crt_moduli": (ctypes.c_int, [_u64, _u32, ctypes.POINTER(_u32), ctypes.POINTER(_u32)]),
     "polymul_negacyclic_shared": (ctypes.c_int, [_vp, _vp, _vp, _u64, _u32, _u64, _vp]),
     "polymul_negacyclic_rns_shared": (ctypes.c_int, [_vp, _vp, _vp, _u64, _vp, _u32, _u64, _vp]),
     "polymul_negacyclic_u64_shared": (ctypes.c_int, [_vp, _vp, _vp, _u64, _u64, _u64, _vp]),
@@ -183,6 +186,35 @@ def polymul_negacyclic_rns(a, b, qs, out=None, stream=None):
                                               n, ctypes.cast(qarr, ctypes.c_void_p), L, batch, _stream(stream))
     _check(st, "polymul_negacyclic_rns")
     return c
+
+
+def polymul_negacyclic_crt(a, b, q, out=None, stream=None):
+    """c = a*b in Z_q[x]/(x^n+1) through small-modulus residues and the CRT (32-bit words, n <= 4096)."""
+    return _binary("polymul_negacyclic_crt", a, b, q, out, stream, 4)
+
+
+def polymul_negacyclic_rns_crt(a, b, qs, out=None, stream=None):
+    """RNS form [batch, L, n] of polymul_negacyclic_crt; channel l is taken mod qs[l]."""
+    import torch
+    if a.shape != b.shape or a.dim() != 3:
+        raise ValueError("a and b must be [batch, L, n]")
+    batch, L, n = a.shape
+    if len(qs) != L:
+        raise ValueError("need one modulus per channel")
+    c = torch.empty_like(a) if out is None else out
+    qarr = (ctypes.c_uint32 * L)(*[int(x) for x in qs])
+    st = load_library().polymul_negacyclic_rns_crt(_words(a, 4, "a"), _words(b, 4, "b"), _words(c, 4, "out"),
+                                                  n, ctypes.cast(qarr, ctypes.c_void_p), L, batch, _stream(stream))
+    _check(st, "polymul_negacyclic_rns_crt")
+    return c
+
+
+def polymul_crt_moduli(n, q):
+    """The small co-prime moduli polymul_negacyclic_crt uses for (n, q), largest first."""
+    arr = (ctypes.c_uint32 * 11)()
+    cnt = ctypes.c_uint32()
+    _check(load_library().polymul_crt_moduli(int(n), int(q), arr, ctypes.byref(cnt)), "polymul_crt_moduli")
+    return [int(arr[i]) for i in range(cnt.value)]
 
 
 def _shared(name, a, b, q, out, stream, nbytes):

@@ -15,6 +15,7 @@
 #include "pm_stream.h"
 #include "pm_grouped.h"
 #include "pm_karatsuba.h"
+#include "pm_crt.h"
 #include "pm_wide_host.h"
 
 using namespace pm;
@@ -160,7 +161,7 @@ int limbs32(const uint32_t* qs, uint32_t lc) {
 polymul_status fill_mfma32(Mfma32Params& P, const uint32_t* a, const uint32_t* b, uint32_t* c, uint32_t n,
                            const uint32_t* qs, uint32_t lc, uint32_t nq_total, uint32_t l0, uint64_t nprod, int L,
                            uint32_t t, uint32_t* lds, bool cyclic = false, uint32_t lrep = 1,
-                           bool b_shared = false) {
+                           bool b_shared = false, int planes = 0) {
   if (!tile_ok(n, t)) return POLYMUL_EINVAL;
   const Geometry32 g = geometry32(n, t);
   P = Mfma32Params{};
@@ -176,7 +177,8 @@ polymul_status fill_mfma32(Mfma32Params& P, const uint32_t* a, const uint32_t* b
   P.a_plane = g.a_plane; P.b_rows = g.b_rows; P.b_rowstride = g.b_rowstride; P.b_plane = g.b_plane;
   P.E = g.E;
   P.lc = lc; P.nq_total = nq_total; P.l0 = l0; P.lrep = lrep;
-  P.slot_bytes = (uint32_t)L * (g.a_plane + g.b_plane);
+  // byte planes per operand: one per limb, or one per small modulus on the RNS-CRT path
+  P.slot_bytes = (uint32_t)(planes ? planes : L) * (g.a_plane + g.b_plane);
   // Epilogue choice: the one-reduction form needs sum_s P_s * n * 2^14 * |rcent_s| < 2^62,
   // P_s = number of limb pairs (i, j) with i + j = s.
   bool fast = true;
@@ -258,6 +260,115 @@ polymul_status launch_shared(const Mfma32Params& P, int L, uint64_t batch, hipSt
     case 2: return launch_shared_L<2>(P, C, (uint32_t)grid, (uint32_t)lds, s);
     case 3: return launch_shared_L<3>(P, C, (uint32_t)grid, (uint32_t)lds, s);
     default: return launch_shared_L<4>(P, C, (uint32_t)grid, (uint32_t)lds, s);
+  }
+}
+
+// ------------------------------------------- small-modulus RNS with CRT
+// ExtractModuli (Algorithm 1, RNS base rules of Sec. 2.6): co-prime integers
+// <= 256 taken largest first until their product exceeds 2 B (1 + 2^-16),
+// B = n floor(qmax / 2)^2 the largest |X_j| of a centred negacyclic sum.
+// `pad` > 0 keeps taking moduli up to that count.  Returns the count, 0 if
+// kMaxCh moduli are not enough.
+uint32_t crt_moduli(uint64_t n, uint32_t qmax, uint32_t* m, uint32_t pad = 0) {
+  const unsigned __int128 h = qmax / 2;
+  const unsigned __int128 B = (unsigned __int128)n * h * h;
+  const unsigned __int128 bound = 2 * B + ((2 * B) >> 16) + 1;
+  unsigned __int128 prod = 1;
+  uint32_t C = 0;
+  for (uint32_t cand = 256; cand >= 2 && C < (uint32_t)kMaxCh; --cand) {
+    bool coprime = true;
+    for (uint32_t i = 0; i < C && coprime; ++i) {
+      uint32_t x = cand, y = m[i];
+      while (y) { const uint32_t t = x % y; x = y; y = t; }
+      coprime = x == 1;
+    }
+    if (!coprime) continue;
+    if (prod > bound && C >= pad) break;
+    m[C++] = cand;
+    prod *= cand;
+  }
+  return prod > bound ? C : 0;
+}
+
+polymul_status fill_crt(CrtConsts& K, const uint32_t* qs, uint32_t lc, uint64_t n, uint32_t pad) {
+  if (lc > (uint32_t)kMaxQC) return POLYMUL_EUNSUPPORTED;
+  uint32_t qmax = 0;
+  for (uint32_t i = 0; i < lc; ++i) qmax = std::max(qmax, qs[i]);
+  K = CrtConsts{};
+  K.C = crt_moduli(n, qmax, K.m, pad);
+  if (K.C == 0) return POLYMUL_EUNSUPPORTED;
+  unsigned __int128 M = 1;
+  for (uint32_t c = 0; c < K.C; ++c) M *= K.m[c];
+  for (uint32_t c = 0; c < K.C; ++c) {
+    const uint32_t mc = K.m[c];
+    const unsigned __int128 Mc = M / mc;
+    const uint32_t r = (uint32_t)(Mc % mc);
+    uint32_t y = 0;
+    for (uint32_t k = 1; k < mc; ++k)
+      if ((uint64_t)r * k % mc == 1) { y = k; break; }
+    if (y == 0 && mc > 1) return POLYMUL_EDEVICE;  // unreachable for co-prime moduli
+    K.y[c] = y;
+    K.magic[c] = (uint32_t)((1ull << 32) / mc);
+    K.off[c] = (uint32_t)((1ull << 31) % mc);
+    K.invm[c] = 1.0f / (float)mc;
+    for (uint32_t i = 0; i < lc; ++i) K.w[i][c] = (uint32_t)(Mc % qs[i]);
+  }
+  for (uint32_t i = 0; i < lc; ++i) K.Mq[i] = (uint32_t)(M % qs[i]);
+  return POLYMUL_OK;
+}
+
+template <int C, bool SMALL> const void* k_crt() { return (const void*)crt_group_kernel<C, SMALL>; }
+
+template <int C, bool SMALL>
+polymul_status launch_crt_C(const Mfma32Params& P, const CrtConsts& K, uint32_t lds, hipStream_t s) {
+  if (allow_lds<k_crt<C, SMALL>>() != POLYMUL_OK) return POLYMUL_EDEVICE;
+  const uint64_t groups = ((P.nprod << P.log2U) + 3) / 4;
+  if (groups > 0x7FFFFFFFull) return POLYMUL_EUNSUPPORTED;
+  hipLaunchKernelGGL((crt_group_kernel<C, SMALL>), dim3((uint32_t)groups), dim3(kThreads), lds, s, P, K);
+  return launch_status();
+}
+
+// Channel counts with a kernel instance; a product needing fewer moduli takes
+// the next count up (the extra moduli only enlarge M).
+constexpr uint32_t kCrtCounts[] = {2, 4, 6, 8, 9, 10, 11};
+
+// nprod products (i -> global (i/lc)*nq_total + l0 + i%lc) through the small-modulus RNS.
+polymul_status run_crt(const uint32_t* a, const uint32_t* b, uint32_t* c, uint32_t n, const uint32_t* qs,
+                       uint32_t lc, uint32_t nq_total, uint32_t l0, uint64_t nprod, hipStream_t s) {
+  if (n > 4096) return POLYMUL_EUNSUPPORTED;  // C residue planes of both operands no longer fit in LDS
+  const bool small = n < 4;
+  CrtConsts K;
+  polymul_status st = fill_crt(K, qs, lc, n, 0);
+  if (st != POLYMUL_OK) return st;
+  uint32_t want = small ? (uint32_t)kMaxCh : K.C;
+  for (uint32_t cc : kCrtCounts)
+    if (cc >= want) { want = cc; break; }
+  if (want != K.C) {
+    st = fill_crt(K, qs, lc, n, want);
+    if (st != POLYMUL_OK) return st;
+    if (K.C != want) return POLYMUL_EUNSUPPORTED;
+  }
+  const int C = (int)K.C;
+  // the largest tile side whose planes fit (fewest staged bytes)
+  Mfma32Params P;
+  uint32_t lds = 0;
+  st = POLYMUL_EUNSUPPORTED;
+  const uint32_t t0 = n <= 32 ? n : std::min<uint32_t>(128, n);
+  for (uint32_t t = t0; t >= (n <= 32 ? n : 32u); t /= 2) {
+    st = fill_mfma32(P, a, b, c, n, qs, lc, nq_total, l0, nprod, 4, t, &lds, false, 1, false, C);
+    if (st == POLYMUL_EINVAL) return st;
+    if (st == POLYMUL_OK) break;
+    if (n <= 32) break;
+  }
+  if (st != POLYMUL_OK) return st;
+  switch (C) {
+    case 2: return launch_crt_C<2, false>(P, K, lds, s);
+    case 4: return launch_crt_C<4, false>(P, K, lds, s);
+    case 6: return launch_crt_C<6, false>(P, K, lds, s);
+    case 8: return launch_crt_C<8, false>(P, K, lds, s);
+    case 9: return launch_crt_C<9, false>(P, K, lds, s);
+    case 10: return launch_crt_C<10, false>(P, K, lds, s);
+    default: return small ? launch_crt_C<11, true>(P, K, lds, s) : launch_crt_C<11, false>(P, K, lds, s);
   }
 }
 
@@ -622,6 +733,41 @@ polymul_status polymul_cyclic_u64(const uint64_t* a, const uint64_t* b, uint64_t
   polymul_status st = check_arrays(a, b, c, n, batch, 1, 8, &bytes);
   if (st != POLYMUL_OK || batch == 0) return st;
   return run_stream<uint64_t>(a, b, c, (uint32_t)n, &q, 1, 1, 0, batch, stream, true);
+}
+
+polymul_status polymul_crt_moduli(uint64_t n, uint32_t q, uint32_t* moduli, uint32_t* count) {
+  if (!moduli || !count || !is_pow2(n) || n > 65536 || q < 2) return POLYMUL_EINVAL;
+  uint32_t m[kMaxCh];
+  const uint32_t C = crt_moduli(n, q, m);
+  if (C == 0) return POLYMUL_EUNSUPPORTED;
+  for (uint32_t i = 0; i < C; ++i) moduli[i] = m[i];
+  *count = C;
+  return POLYMUL_OK;
+}
+
+polymul_status polymul_negacyclic_crt(const uint32_t* a, const uint32_t* b, uint32_t* c, uint64_t n, uint32_t q,
+                                      uint64_t batch, hipStream_t stream) {
+  if (q < 2) return POLYMUL_EINVAL;
+  uint64_t bytes;
+  polymul_status st = check_arrays(a, b, c, n, batch, 1, 4, &bytes);
+  if (st != POLYMUL_OK || batch == 0) return st;
+  return run_crt(a, b, c, (uint32_t)n, &q, 1, 1, 0, batch, stream);
+}
+
+polymul_status polymul_negacyclic_rns_crt(const uint32_t* a, const uint32_t* b, uint32_t* c, uint64_t n,
+                                          const uint32_t* q, uint32_t L, uint64_t batch, hipStream_t stream) {
+  if (L == 0 || !q) return POLYMUL_EINVAL;
+  for (uint32_t l = 0; l < L; ++l)
+    if (q[l] < 2) return POLYMUL_EINVAL;
+  uint64_t bytes;
+  polymul_status st = check_arrays(a, b, c, n, batch, L, 4, &bytes);
+  if (st != POLYMUL_OK || batch == 0) return st;
+  for (uint32_t l0 = 0; l0 < L; l0 += kMaxQC) {
+    const uint32_t lc = std::min(L - l0, (uint32_t)kMaxQC);
+    st = run_crt(a, b, c, (uint32_t)n, q + l0, lc, L, l0, batch * lc, stream);
+    if (st != POLYMUL_OK) return st;
+  }
+  return POLYMUL_OK;
 }
 
 polymul_status polymul_negacyclic_shared(const uint32_t* a, const uint32_t* b, uint32_t* c, uint64_t n,

@@ -195,3 +195,19 @@ def test_shared_operand_arguments():
     assert call(k, A, B, C, 256, ctypes.cast(bad, ctypes.c_void_p), 2, 4, None) == EINVAL
     assert call(k, A, B, B + 2 * 256 * 4 - 16, 256, qp, 2, 4, None) == EALIAS  # c overlaps the end of b
     assert call(k, None, None, None, 256, qp, 2, 0, None) == 0
+
+
+def test_crt_arguments():
+    assert call("polymul_negacyclic_crt", A, B, C, 255, 17, 1, None) == EINVAL
+    assert call("polymul_negacyclic_crt", A, B, C, 256, 1, 1, None) == EINVAL
+    assert call("polymul_negacyclic_crt", A, B, A, 256, 17, 1, None) == EALIAS
+    assert call("polymul_negacyclic_crt", A, B, C, 8192, 17, 1, None) == EUNSUPPORTED  # planes exceed LDS
+    assert call("polymul_negacyclic_crt", None, None, None, 256, 17, 0, None) == 0
+    qs = (ctypes.c_uint32 * 2)(17, 1)
+    assert call("polymul_negacyclic_rns_crt", A, B, C, 256, ctypes.cast(qs, ctypes.c_void_p), 2, 1, None) == EINVAL
+    out = (ctypes.c_uint32 * 11)()
+    cnt = ctypes.c_uint32()
+    assert call("polymul_crt_moduli", 256, 1, out, ctypes.byref(cnt)) == EINVAL
+    assert call("polymul_crt_moduli", 100, 17, out, ctypes.byref(cnt)) == EINVAL
+    assert call("polymul_crt_moduli", 256, 17, None, ctypes.byref(cnt)) == EINVAL
+    assert call("polymul_crt_moduli", 65536, 0xFFFFFFFF, out, ctypes.byref(cnt)) == 0 and cnt.value <= 11
