@@ -7,8 +7,9 @@ q_i = 1 mod 2n, i.e. 2048 independent limb-products) through
 polymul_negacyclic_rns, inputs already resident in HBM.  Prints one JSON line
 on stdout.  The same batch also goes through the Karatsuba route
 (polymul_negacyclic_rns_karatsuba), the shared-operand route with one b per
-channel (polymul_negacyclic_rns_shared), both reported beside the headline, and
-the plain integer kernel.  --all also times the other workloads (to stderr).
+channel (polymul_negacyclic_rns_shared) and the paper's small-modulus RNS with
+CRT (polymul_negacyclic_rns_crt), all reported beside the headline, and the
+plain integer kernel.  --all also times the other workloads (to stderr).
 """
 import argparse
 import hashlib
@@ -202,6 +203,23 @@ def main():
               "kernel": "mfma32_shared_kernel<4>"}
     del bs, cs
 
+    # the paper's own coefficient method: 8-bit co-prime moduli and CRT (9 residue channels here)
+    cc = torch.empty_like(a)
+    ms_c = time_steps(lambda: pm.polymul_negacyclic_rns_crt(a, b, w.qs, out=cc), args.steps, args.warmup)
+    chans = len(pm.polymul_crt_moduli(n, max(w.qs)))
+    # LDS read instructions per MFMA: five dwords of A (two ds_read2_b32, one ds_read_b32) and a
+    # ds_read_b128 of B, one fragment each per residue channel; bytes per wave64 MFMA:
+    lds_bytes = products * 4 * chans * (n // 32) * 64 * (20 + 16)  # 4 tiles, n/32 K-steps
+    crt = {"value": products / (ms_c / 1e3), "unit": "polymuls/s", "ms_per_step": ms_c,
+           "vs_limbs": ms / ms_c, "moduli": pm.polymul_crt_moduli(n, max(w.qs)),
+           "mfma_ops_per_step": 2 * chans * n * n * products,
+           "lds_read_tb_per_s": lds_bytes / (ms_c / 1e3) / 1e12, "bound": "lds",
+           "bit_identical_to_limbs": None, "kernel": f"crt_group_kernel<{chans},false>"}
+    pm.polymul_negacyclic_rns(a, b, w.qs, out=c)
+    torch.cuda.synchronize()
+    crt["bit_identical_to_limbs"] = bool(torch.equal(cc, c))
+    del cc
+
     limbs = 4  # int8 limbs per operand for a 30-bit modulus
     ops_per_product = 2 * limbs * limbs * n * n
     achieved_tops = ops_per_product * products / (ms / 1e3) / 1e12
@@ -224,6 +242,7 @@ def main():
                      "frac": achieved_tops / PEAK_INT8_TOPS, "traffic": measured_traffic(), "kernel": KERNEL},
         "karatsuba": kara,
         "shared_operand": shared,
+        "rns_crt": crt,
         "plain_int": {"value": plain_value, "unit": "polymuls/s", "ms_per_step": ms_plain,
                       "mfma_speedup": value / plain_value},
     }
