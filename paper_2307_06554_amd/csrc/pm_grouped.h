@@ -46,7 +46,10 @@ void grouped_kernel(const GroupJob* __restrict__ jobs, const WorkItem* __restric
     if (it >= nitems) break;  // uniform: every wave leaves together
     const WorkItem w = items[it];
     const GroupJob& job = jobs[w.group];
-    if (job.kind == kJobResident) resident_group<L, false>(job.rp, w.index, smem);
+    if (job.kind == kJobResident) {
+      if (job.rp.kparts > 1) resident_group_split<L>(job.rp, w.index, smem);
+      else resident_group<L, false>(job.rp, w.index, smem);
+    }
     else stream_block<L, uint32_t>(job.sp, w.index, smem);
     __syncthreads();  // LDS is reused by the next item
   }

@@ -53,6 +53,11 @@ struct Mfma32Params {
   uint32_t fast_epilogue;  // 1: sum_s T_s * rcent[s] is known to stay below 2^62 in magnitude
   uint32_t cyclic;         // 1: ring Z_q[x]/(x^n - 1): wrapped terms keep their sign
   uint32_t b_shared;       // 1: one b per modulus channel, b + (l0 + channel) * n, for every product
+  // K split across workgroups (grouped plans, groups of one product only): group g is
+  // cut into kparts runs of K-steps; run p stores its residues where c's would go in
+  // part_ws + p * nprod * n, and a separate kernel adds the runs up mod q.
+  uint32_t kparts;
+  uint32_t* part_ws;       // [kparts][nprod][n]
   ModQ32 mods[kMaxQ];
   int32_t rcent[kMaxQ][8];  // 2^(8s) mod q as a centred residue, s < 2L-1
 };
@@ -283,14 +288,15 @@ __device__ __forceinline__ void mfma_step_pp(v16i (&acc)[2 * L - 1], const v4i (
 // step's A reads into the freed raw registers, then the MFMAs (which refill B).
 template <int L>
 __device__ __forceinline__ void mfma32_tile(const Mfma32Params& P, const uint8_t* aplane, const uint8_t* bplane,
-                                            int z0, int u0, int v_lo, v16i (&acc)[2 * L - 1]) {
+                                            int z0, int u0, int v_lo, v16i (&acc)[2 * L - 1], int st_lo = 0,
+                                            int st_hi = -1) {
   const int lane = threadIdx.x & 63;
   const int zl = lane & 31, g = lane >> 5;
   // A: lane reads reversed positions S .. S+15 with S = E - (d t + z - w0 - 16 g).
   const int S0 = (int)P.E - (z0 + zl) + 16 * g;
   // B: lane reads row (u - d) - v_lo, bytes w0 + 16 g .. + 15.
   const int B0 = (u0 + zl - v_lo) * (int)P.b_rowstride + 16 * g;
-  const int steps = (int)(P.r << P.log2spd);
+  const int steps = st_hi < 0 ? (int)(P.r << P.log2spd) : st_hi;  // one past the last K-step
   const int rs = (int)P.b_rowstride;
   const uint32_t a_plane = P.a_plane, b_plane = P.b_plane;
 #pragma unroll
@@ -303,12 +309,12 @@ __device__ __forceinline__ void mfma32_tile(const Mfma32Params& P, const uint8_t
   auto clamp = [&](int st) { return st < steps ? st : steps - 1; };
   uint32_t araw[L][5];
   v4i a0[L], a1[L], b[L];
-  const int S_first = S_of(0);
+  const int S_first = S_of(st_lo);
   araw_load<L>(araw, aplane, a_plane, S_first);
-  b_load<L>(b, bplane, b_plane, B_of(0));
+  b_load<L>(b, bplane, b_plane, B_of(st_lo));
   a_align<L>(a0, araw, (uint32_t)(S_first & 3));
-  araw_load<L>(araw, aplane, a_plane, S_of(clamp(1)));
-  int st = 0;
+  araw_load<L>(araw, aplane, a_plane, S_of(clamp(st_lo + 1)));
+  int st = st_lo;
   for (; st + 1 < steps; st += 2) {
     mfma_step_pp<L>(acc, a0, a1, araw, (uint32_t)(S_of(st + 1) & 3), aplane, a_plane, S_of(clamp(st + 2)), b,
                     bplane, b_plane, B_of(st + 1));
@@ -323,12 +329,8 @@ __device__ __forceinline__ void mfma32_tile(const Mfma32Params& P, const uint8_t
 // Recombination c = sum_s T_s 2^(8s) mod q of the 16 outputs a lane holds, then
 // the stores.
 template <int L>
-__device__ __forceinline__ void mfma32_epilogue(const Mfma32Params& P, uint64_t gprod, const ModQ32& m,
-                                                const int32_t* rc, int z0, int u0, const v16i (&acc)[2 * L - 1]) {
-  const int lane = threadIdx.x & 63;
-  const int g = lane >> 5;
-  const int u = u0 + (lane & 31);
-  uint32_t out[16];
+__device__ __forceinline__ void mfma32_reduce(const Mfma32Params& P, const ModQ32& m, const int32_t* rc,
+                                              const v16i (&acc)[2 * L - 1], uint32_t (&out)[16]) {
 #pragma unroll
   for (int rr = 0; rr < 16; ++rr) {
     if (P.fast_epilogue) {
@@ -345,6 +347,13 @@ __device__ __forceinline__ void mfma32_epilogue(const Mfma32Params& P, uint64_t 
       out[rr] = v;
     }
   }
+}
+// The 16 residues of a lane to c: z = z0 + 8 blk + 4 g + e, u = u0 + (lane & 31).
+__device__ __forceinline__ void mfma32_store(const Mfma32Params& P, uint64_t gprod, int z0, int u0,
+                                             const uint32_t (&out)[16]) {
+  const int lane = threadIdx.x & 63;
+  const int g = lane >> 5;
+  const int u = u0 + (lane & 31);
   if (u >= (int)P.r) return;
   uint32_t* C = P.c + gprod * P.n;
 #pragma unroll
@@ -358,6 +367,13 @@ __device__ __forceinline__ void mfma32_epilogue(const Mfma32Params& P, uint64_t 
         if (zb + e < (int)P.t) C[(size_t)u * P.t + zb + e] = out[4 * blk + e];
     }
   }
+}
+template <int L>
+__device__ __forceinline__ void mfma32_epilogue(const Mfma32Params& P, uint64_t gprod, const ModQ32& m,
+                                                const int32_t* rc, int z0, int u0, const v16i (&acc)[2 * L - 1]) {
+  uint32_t out[16];
+  mfma32_reduce<L>(P, m, rc, acc, out);
+  mfma32_store(P, gprod, z0, u0, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -554,6 +570,64 @@ __device__ __forceinline__ void resident_group(const Mfma32Params& P, uint64_t g
   uint32_t li;
   const uint64_t gprod = global_product(P, prod, &li);
   mfma32_epilogue<L>(P, gprod, P.mods[li], P.rcent[li], 32 * zt, 32 * ut, acc);
+}
+
+// One run of a K-split group (one product, U >= 4: every wave has a tile):
+// K-steps [part, part + 1) * steps / kparts of all four tiles, residues stored
+// in the run's copy of c.
+template <int L>
+__device__ __forceinline__ void resident_group_split(const Mfma32Params& P, uint32_t item, uint8_t* smem) {
+  const uint32_t grp = item / P.kparts, part = item - grp * P.kparts;
+  const uint32_t U = 1u << P.log2U;
+  const GroupInfo gi = group_info(P, grp);
+  {
+    const uint32_t nitems = gi.nslots * (P.n >> 1);
+    for (uint32_t base = 0; base < nitems; base += kPrefetch * kThreads) {
+      uint4 pf[kPrefetch];
+#pragma unroll
+      for (int k = 0; k < kPrefetch; ++k) {
+        const uint32_t i = base + threadIdx.x + k * kThreads;
+        const uint4* src = i < nitems ? item_src(P, gi, i) : nullptr;
+        pf[k] = src ? *src : make_uint4(0, 0, 0, 0);
+      }
+#pragma unroll
+      for (int k = 0; k < kPrefetch; ++k) {
+        const uint32_t i = base + threadIdx.x + k * kThreads;
+        if (i < nitems) item_store<L>(P, gi, smem, i, pf[k]);
+      }
+    }
+    stage_zero_fill<L>(P, gi, smem);
+  }
+  __syncthreads();
+  const uint32_t wave = threadIdx.x >> 6;
+  const uint64_t unit = (uint64_t)grp * 4 + wave;
+  const uint64_t prod = unit >> P.log2U;
+  const uint32_t tile = (uint32_t)(unit & (U - 1));
+  const int zt = (int)(tile % P.tz), ut = (int)(tile / P.tz);
+  const int steps = (int)(P.r << P.log2spd);
+  const int st_lo = (int)(part * (uint32_t)steps / P.kparts), st_hi = (int)((part + 1) * (uint32_t)steps / P.kparts);
+  v16i acc[2 * L - 1];
+  mfma32_tile<L>(P, smem, smem + L * P.a_plane, 32 * zt, 32 * ut, gi.v_lo, acc, st_lo, st_hi);
+  uint32_t li;
+  const uint64_t gprod = global_product(P, prod, &li);
+  uint32_t out[16];
+  mfma32_reduce<L>(P, P.mods[li], P.rcent[li], acc, out);
+  Mfma32Params Q = P;  // the run's copy of c
+  Q.c = P.part_ws + (uint64_t)part * P.nprod * P.n;
+  mfma32_store(Q, gprod, 32 * zt, 32 * ut, out);
+}
+
+// c = sum of the kparts runs' residues mod q, word by word (one plan job).
+__global__ __launch_bounds__(256) void split_sum_kernel(const uint32_t* __restrict__ ws, uint32_t* __restrict__ c,
+                                                        uint64_t words, uint32_t kparts, ModQ32 m) {
+  const uint64_t i = ((uint64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+  if (i >= words) return;  // words is a multiple of 4
+  uint64_t s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  for (uint32_t p = 0; p < kparts; ++p) {
+    const uint4 x = *(const uint4*)(ws + (uint64_t)p * words + i);
+    s0 += x.x; s1 += x.y; s2 += x.z; s3 += x.w;
+  }
+  *(uint4*)(c + i) = make_uint4(reduce_u64(s0, m), reduce_u64(s1, m), reduce_u64(s2, m), reduce_u64(s3, m));
 }
 
 // One group of four 32x32 tiles per workgroup.

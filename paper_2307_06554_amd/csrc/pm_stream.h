@@ -45,6 +45,11 @@ struct StreamParams {
   uint32_t lrep;              // > 1: product i is global i with modulus (i/lrep)%lc
   uint32_t b_shared;          // 1: one b per channel, b + (l0 + channel) * n, for every product
   uint32_t cyclic;            // 1: ring Z_q[x]/(x^n - 1): wrapped terms keep their sign
+  // K split across workgroups (grouped plans): block (product, u-block) is cut into kparts
+  // runs of nchunks / kparts chunks; run p stores its residues where c's would go in
+  // part_ws + p * nprod * n, and a separate kernel adds the runs up mod q.
+  uint32_t kparts;
+  void* part_ws;              // [kparts][nprod][n] words
   ModQ64 mods[kMaxQS];
 };
 
@@ -138,7 +143,8 @@ __device__ __forceinline__ ChunkItems chunk_items(const StreamParams& P, int c, 
   ci.a_m0 = ((I1 + 1) >> 2) - ci.a_groups;
   ci.row_groups = (int)(P.rowlen >> 2);
   if (first) {
-    ci.b_v0 = U0 - (int)P.dc + 1;
+    // every row this chunk reads: v = u - d for the block's 64 u and the chunk's dc d
+    ci.b_v0 = U0 - (c + 1) * (int)P.dc + 1;
     ci.b_rows = 63 + (int)P.dc;
   } else {
     ci.b_v0 = U0 - (c + 1) * (int)P.dc + 1;
@@ -252,7 +258,11 @@ __device__ __forceinline__ void stream_flush(v16i (&acc)[2 * L - 1], W (&res)[16
 // One 64 (z) x 64 (u) block of one product, the whole K loop.  Block index
 // wg = product * ublocks + u-block.
 template <int L, typename W>
-__device__ __forceinline__ void stream_block(const StreamParams& P, uint64_t wg, uint8_t* smem) {
+__device__ __forceinline__ void stream_block(const StreamParams& P, uint64_t item, uint8_t* smem) {
+  const uint64_t wg = item / P.kparts;  // block (product, u-block)
+  const uint32_t part = (uint32_t)(item - wg * P.kparts);
+  const int cpp = (int)(P.nchunks / P.kparts);
+  const int c0 = (int)part * cpp, c1 = c0 + cpp;
   const uint64_t prod = wg / P.ublocks;
   const int U0 = 64 * (int)(wg - prod * P.ublocks);
   const uint32_t li = P.lrep > 1 ? (uint32_t)((prod / P.lrep) % P.lc) : (uint32_t)(prod % P.lc);
@@ -268,17 +278,18 @@ __device__ __forceinline__ void stream_block(const StreamParams& P, uint64_t wg,
   const int zl = lane & 31, g = lane >> 5;
   const int t = (int)P.t, rs = (int)P.rs;
 
-  // ---- chunk 0: everything it needs, loaded synchronously
+  // ---- first chunk: everything it needs, loaded synchronously
   {
-    const ChunkItems ci = chunk_items(P, 0, U0, true);
-    const int I1 = ((int)P.dc - 1) * t + 32 * (int)P.tz - 1;
+    const ChunkItems ci = chunk_items(P, c0, U0, true);
+    const int I1 = (c0 * (int)P.dc + (int)P.dc - 1) * t + 32 * (int)P.tz - 1;
+    uint8_t* abuf0 = smem + (c0 & 1) * (L * P.a_win);
     for (int i = threadIdx.x; i < ci.count(); i += kStreamThreads) {
       const StreamItem it = ci.item(i);
       bool neg;
       const W* src = item_ptr<W>(P, it, gp, bgp, &neg);
       Quad<W> x{};
       if (src) x = load_quad<W>(src);
-      item_write<L, W>(P, it, x, src != nullptr, neg, gp, bgp, m, smem, ring, I1);
+      item_write<L, W>(P, it, x, src != nullptr, neg, gp, bgp, m, abuf0, ring, I1);
     }
   }
   __syncthreads();
@@ -295,9 +306,9 @@ __device__ __forceinline__ void stream_block(const StreamParams& P, uint64_t wg,
   constexpr int kItems = 3;  // items per thread carried over a chunk (dc <= 16, t <= 64)
   const int steps = (int)(P.dc << P.log2spd);
 
-  for (int c = 0; c < (int)P.nchunks; ++c) {
+  for (int c = c0; c < c1; ++c) {
     // ---- issue the next chunk's loads
-    const bool more = c + 1 < (int)P.nchunks;
+    const bool more = c + 1 < c1;
     ChunkItems cn{};
     Quad<W> pf[kItems];
     bool pl[kItems], pn[kItems];
@@ -339,7 +350,7 @@ __device__ __forceinline__ void stream_block(const StreamParams& P, uint64_t wg,
         araw_load<L>(araw, abuf, P.a_win, S);
         mfma_step<L>(acc, af, b, ring, kRing * P.rs, B_of(sn));
       }
-      if (!more || (c + 1) % (int)P.flush_every == 0) stream_flush<L, W>(acc, res, m);
+      if (!more || (c + 1 - c0) % (int)P.flush_every == 0) stream_flush<L, W>(acc, res, m);
     }
     if (!more) break;
     // ---- convert and write the next chunk (its A buffer and ring rows are not read now)
@@ -367,7 +378,7 @@ __device__ __forceinline__ void stream_block(const StreamParams& P, uint64_t wg,
   if (!active) return;
   const int u = u0 + zl;
   if (u >= (int)P.r) return;
-  W* C = (W*)P.c + gp * P.n;
+  W* C = (P.kparts > 1 ? (W*)P.part_ws + (uint64_t)part * P.nprod * P.n : (W*)P.c) + gp * P.n;
 #pragma unroll
   for (int rr = 0; rr < 16; ++rr) {
     const int z = z0 + 8 * (rr >> 2) + 4 * g + (rr & 3);

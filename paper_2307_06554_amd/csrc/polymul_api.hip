@@ -199,6 +199,7 @@ polymul_status fill_mfma32(Mfma32Params& P, const uint32_t* a, const uint32_t* b
   P.fast_epilogue = fast ? 1u : 0u;
   P.cyclic = cyclic ? 1u : 0u;
   P.b_shared = b_shared ? 1u : 0u;
+  P.kparts = 1;
   *lds = P.slots * P.slot_bytes;
   return *lds <= kMaxLds ? POLYMUL_OK : POLYMUL_EUNSUPPORTED;
 }
@@ -405,6 +406,7 @@ polymul_status fill_stream(StreamParams& P, const void* a, const void* b, void* 
   P.lc = lc; P.nq_total = nq_total; P.l0 = l0; P.lrep = lrep;
   P.cyclic = cyclic ? 1u : 0u;
   P.b_shared = b_shared ? 1u : 0u;
+  P.kparts = 1;
   for (uint32_t i = 0; i < lc; ++i) P.mods[i] = make_mod64(qs[i], L);
   *lds = P.lds_b + (uint32_t)L * kRing * P.rs;
   return *lds <= kMaxLds ? POLYMUL_OK : POLYMUL_EUNSUPPORTED;
@@ -480,6 +482,15 @@ struct polymul_plan {
   GroupJob* d_jobs = nullptr;       // device job table
   WorkItem* d_items = nullptr;      // device work list (largest first)
   uint32_t* d_counter = nullptr;    // queue counter
+  void* d_part_ws = nullptr;        // residues of K-split runs
+  struct SplitSum {                 // one K-split job: c = sum of its runs mod q
+    const uint32_t* ws;
+    uint32_t* c;
+    uint64_t words;
+    uint32_t kparts;
+    ModQ32 m;
+  };
+  std::vector<SplitSum> sums;
   uint32_t nitems = 0;
   uint32_t lds = 0;                 // dynamic LDS of the grouped launch
   uint32_t grid = 0;
@@ -509,6 +520,13 @@ polymul_status plan_launch(const polymul_plan* p, hipStream_t s) {
                        p->nitems, p->d_counter);
     polymul_status st = launch_status();
     if (st != POLYMUL_OK) return st;
+    for (const auto& sum : p->sums) {
+      const uint64_t blocks = (sum.words / 4 + 255) / 256;
+      hipLaunchKernelGGL(split_sum_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, sum.ws, sum.c, sum.words,
+                         sum.kparts, sum.m);
+      st = launch_status();
+      if (st != POLYMUL_OK) return st;
+    }
   }
   for (size_t i = 0; i < p->wide.size(); ++i) {
     polymul_status st = p->wide_L[i] == 4 ? launch_stream_L<4, uint64_t, 2>(p->wide[i], p->wide_lds[i], s)
@@ -526,6 +544,7 @@ void plan_free(polymul_plan* p) {
   if (p->d_jobs) (void)hipFree(p->d_jobs);
   if (p->d_items) (void)hipFree(p->d_items);
   if (p->d_counter) (void)hipFree(p->d_counter);
+  if (p->d_part_ws) (void)hipFree(p->d_part_ws);
   delete p;
 }
 
@@ -533,9 +552,23 @@ void plan_free(polymul_plan* p) {
 uint64_t item_cost(const GroupJob& j) {
   if (j.kind == kJobResident) {
     const uint64_t steps = (uint64_t)j.rp.r << j.rp.log2spd;
-    return 4 * steps;  // four tiles
+    return 4 * steps / j.rp.kparts;  // four tiles
   }
-  return (uint64_t)4 * ((uint64_t)j.sp.r << j.sp.log2spd);
+  return (uint64_t)4 * ((uint64_t)j.sp.r << j.sp.log2spd) / j.sp.kparts;
+}
+
+// MFMA work of one unsplit item of a 32-bit group on its default route (resident for
+// n in [4, 4096], streamed otherwise), and the number of such items.
+void default_cost(uint32_t n, uint64_t count, uint64_t* items, uint64_t* cost) {
+  if (n >= 4 && n <= 4096) {
+    const Geometry32 g = geometry32(n, tile_for(n, 4));
+    *items = (count * g.U + 3) / 4;
+    *cost = 4 * (uint64_t)g.r * g.spd;
+  } else {
+    const uint32_t t = n < 64 ? n : 64, r = n / t, spd = t >= 64 ? 2 : 1;
+    *items = count * ((r + 63) / 64);
+    *cost = 4 * (uint64_t)r * spd;
+  }
 }
 
 }  // namespace
@@ -624,6 +657,20 @@ polymul_status polymul_plan_create(polymul_plan** plan, const polymul_group* gro
   p->use_graph = !(flags & POLYMUL_PLAN_NO_GRAPH);
   std::vector<GroupJob> jobs;
   std::vector<WorkItem> items;
+  // Balance (paper Sec. 3 notes the TPU's lack of fine control): the persistent grid
+  // holds two workgroups per CU; the items of a 32-bit group that would cost more
+  // than an even share of the total have their K range cut into runs (resident
+  // groups of one product, or streamed blocks), whose residues a second kernel
+  // adds up mod q.
+  uint64_t total_cost = 0;
+  for (uint32_t g = 0; g < ngroups; ++g) {
+    if (groups[g].elem_bytes != 4 || groups[g].count == 0) continue;
+    uint64_t ni, ci;
+    default_cost((uint32_t)groups[g].n, groups[g].count, &ni, &ci);
+    total_cost += ni * ci;
+  }
+  const uint64_t share = std::max<uint64_t>(64, total_cost / (2ull * device_cus()));
+  uint64_t part_words = 0;
   for (uint32_t g = 0; g < ngroups; ++g) {
     const polymul_group& G = groups[g];
     if (G.count == 0) continue;
@@ -643,19 +690,44 @@ polymul_status polymul_plan_create(polymul_plan** plan, const polymul_group* gro
     const uint32_t q32 = (uint32_t)G.q;
     uint32_t lds = 0;
     polymul_status st;
+    uint64_t ni, ci;
+    default_cost(n, G.count, &ni, &ci);
+    const bool split = ci > share;
     if (n >= 4 && n <= 4096) {
       job.kind = kJobResident;
       st = fill_mfma32(job.rp, (const uint32_t*)G.a, (const uint32_t*)G.b, (uint32_t*)G.c, n, &q32, 1, 1, 0,
                        G.count, 4, tile_for(n, 4), &lds);
+      if (st == POLYMUL_OK && split && job.rp.log2U >= 2) {  // groups of one product: every wave has a tile
+        const uint32_t steps = job.rp.r << job.rp.log2spd;
+        uint32_t k = 1;
+        while (2 * k <= steps && ci / k > share) k *= 2;
+        job.rp.kparts = k;
+        if (k > 1) {
+          // an offset for now; turned into a device pointer once the buffer exists
+          job.rp.part_ws = (uint32_t*)(uintptr_t)part_words;
+          part_words += (uint64_t)k * G.count * n;
+        }
+      }
     } else {
       job.kind = kJobStream;
       const uint64_t q64 = G.q;
       st = fill_stream(job.sp, G.a, G.b, G.c, n, &q64, 1, 1, 0, G.count, 4, &lds);
+      if (st == POLYMUL_OK && split) {
+        const uint64_t scost = 4 * ((uint64_t)job.sp.r << job.sp.log2spd);
+        uint32_t k = 1;
+        while (k < job.sp.nchunks && scost / k > share) k *= 2;
+        job.sp.kparts = k;
+        if (k > 1) {
+          job.sp.part_ws = (void*)(uintptr_t)part_words;
+          part_words += (uint64_t)k * G.count * n;
+        }
+      }
     }
     if (st != POLYMUL_OK) { plan_free(p); return st; }
     p->lds = std::max(p->lds, lds);
     const uint32_t jid = (uint32_t)jobs.size();
-    const uint64_t cnt = job.kind == kJobResident ? ((G.count << job.rp.log2U) + 3) / 4 : G.count * job.sp.ublocks;
+    const uint64_t cnt = job.kind == kJobResident ? ((G.count << job.rp.log2U) + 3) / 4 * job.rp.kparts
+                                                  : G.count * job.sp.ublocks * job.sp.kparts;
     if (cnt + items.size() > 0xFFFFFFFFull) { plan_free(p); return POLYMUL_EUNSUPPORTED; }
     for (uint64_t i = 0; i < cnt; ++i) items.push_back(WorkItem{jid, (uint32_t)i});
     jobs.push_back(job);
@@ -671,6 +743,23 @@ polymul_status polymul_plan_create(polymul_plan** plan, const polymul_group* gro
         hipMalloc((void**)&p->d_counter, 256) != hipSuccess) {
       plan_free(p);
       return POLYMUL_ENOMEM;
+    }
+    if (part_words) {
+      if (hipMalloc(&p->d_part_ws, part_words * 4) != hipSuccess) {
+        plan_free(p);
+        return POLYMUL_ENOMEM;
+      }
+      for (GroupJob& j : jobs) {
+        if (j.kind == kJobStream && j.sp.kparts > 1) {
+          j.sp.part_ws = (uint32_t*)p->d_part_ws + (uintptr_t)j.sp.part_ws;
+          p->sums.push_back({(const uint32_t*)j.sp.part_ws, (uint32_t*)j.sp.c, j.sp.nprod * j.sp.n, j.sp.kparts,
+                             make_mod32((uint32_t)j.sp.mods[0].q, 4)});
+        }
+        if (j.kind == kJobResident && j.rp.kparts > 1) {
+          j.rp.part_ws = (uint32_t*)p->d_part_ws + (uintptr_t)j.rp.part_ws;
+          p->sums.push_back({j.rp.part_ws, j.rp.c, j.rp.nprod * j.rp.n, j.rp.kparts, j.rp.mods[0]});
+        }
+      }
     }
     hipError_t e = hipMemcpy(p->d_jobs, jobs.data(), jobs.size() * sizeof(GroupJob), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p->d_items, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice);

@@ -95,3 +95,35 @@ def test_tile_table_parity(n, t):
         pm.polymul_tune_set(n, 4, 0)
     wv = oracle.negacyclic(a, b, q)
     assert np.array_equal(got, wv), mismatch_report(got, wv)
+
+
+def test_plan_split_k_runs():
+    """A plan dominated by one large product: its K range is cut into runs on
+    several workgroups whose residues the last run adds up; three replays."""
+    rng = np.random.Generator(np.random.PCG64(23))
+    specs = [(65536, 1068236801, 1), (2048, 3329, 3), (256, 17, 50), (8192, (1 << 32) - 5, 2)]
+    groups, host = [], []
+    for n, q, count in specs:
+        a = rng.integers(0, q, size=(count, n), dtype=np.uint64).astype(np.uint32)
+        b = rng.integers(0, q, size=(count, n), dtype=np.uint64).astype(np.uint32)
+        da, db = to_dev(a), to_dev(b)
+        groups.append((da, db, torch.zeros_like(da), n, q))
+        host.append((a, b, q))
+    plan = pm.Plan(groups)
+    big_a, big_b, big_q = host[0]
+    jidx = rng.integers(0, 65536, size=96, dtype=np.uint64)
+    jidx[:4] = [0, 1, 65534, 65535]
+    pidx = np.zeros_like(jidx)
+    want_big = oracle.negacyclic_sample(big_a, big_b, big_q, pidx, jidx)
+    want_rest = [oracle.negacyclic(a, b, q) for (a, b, q) in host[1:]]
+    for rep in range(3):
+        for g in groups:
+            g[2].zero_()
+        plan.execute()
+        torch.cuda.synchronize()
+        got_big = to_host(groups[0][2], np.uint32)[0, jidx.astype(np.int64)]
+        assert np.array_equal(got_big, want_big), f"replay {rep}: " + mismatch_report(got_big, want_big)
+        for (da, db, dc, n, q), wv in zip(groups[1:], want_rest):
+            got = to_host(dc, np.uint32)
+            assert np.array_equal(got, wv), f"replay {rep}, n={n}: " + mismatch_report(got, wv)
+    plan.close()
