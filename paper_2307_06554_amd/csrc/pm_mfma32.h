@@ -393,6 +393,16 @@ struct GroupInfo {
 };
 
 __device__ __forceinline__ uint64_t global_product(const Mfma32Params& P, uint64_t prod, uint32_t* li) {
+  if ((prod >> 32) == 0) {  // 32-bit quotients (the usual case) are much cheaper
+    const uint32_t p32 = (uint32_t)prod;
+    if (P.lrep > 1) {
+      *li = (p32 / P.lrep) % P.lc;
+      return prod;
+    }
+    const uint32_t qt = p32 / P.lc;
+    *li = p32 - qt * P.lc;
+    return (uint64_t)qt * P.nq_total + P.l0 + *li;
+  }
   if (P.lrep > 1) {
     *li = (uint32_t)((prod / P.lrep) % P.lc);
     return prod;
@@ -525,6 +535,41 @@ __device__ __forceinline__ void stage_zero_fill(const Mfma32Params& P, const Gro
   for (uint32_t s = 0; s < gi.nslots; ++s) zero_fill_b<L>(P, smem + s * P.slot_bytes + L * P.a_plane, gi.v_lo);
 }
 
+// Staging for n >= 1024: every run of 256 consecutive items lies in one slot and
+// is all A or all B (n/4 >= 256 items each), so slot, kind and modulus are
+// workgroup-uniform and each thread handles item (run, threadIdx.x).
+template <int L>
+__device__ __forceinline__ void stage_uniform(const Mfma32Params& P, const GroupInfo& gi, uint8_t* smem) {
+  const uint32_t runs_per_slot = P.n >> 9, a_runs = P.n >> 10;  // (n/2) / 256 and (n/4) / 256
+  const uint32_t nruns = gi.nslots * runs_per_slot;
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t r0 = 0; r0 < nruns; r0 += kPrefetch) {
+    uint4 pf[kPrefetch];
+#pragma unroll
+    for (int k = 0; k < kPrefetch; ++k) {
+      const uint32_t run = r0 + k;
+      pf[k] = make_uint4(0, 0, 0, 0);
+      if (run < nruns) {
+        const uint32_t sl = run / runs_per_slot, cr = run - sl * runs_per_slot;
+        const uint64_t gp = slot_gp(gi, sl);
+        if (cr < a_runs) pf[k] = ((const uint4*)(P.a + gp * P.n))[cr * 256 + tid];
+        else pf[k] = ((const uint4*)(P.b + b_product(P, gp, slot_li(gi, sl)) * P.n))[(cr - a_runs) * 256 + tid];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kPrefetch; ++k) {
+      const uint32_t run = r0 + k;
+      if (run < nruns) {
+        const uint32_t sl = run / runs_per_slot, cr = run - sl * runs_per_slot;
+        const ModQ32& m = P.mods[slot_li(gi, sl)];
+        uint8_t* slot = smem + sl * P.slot_bytes;
+        if (cr < a_runs) stage_a_item<L>(P, slot, cr * 256 + tid, pf[k], m);
+        else stage_b_item<L>(P, slot + L * P.a_plane, gi.v_lo, (cr - a_runs) * 256 + tid, pf[k], m);
+      }
+    }
+  }
+}
+
 // One group of four 32x32 tiles: stage the products it touches, then each wave
 // runs its tile.  SMALL: n < 4, staged byte by byte.  Ends with every wave
 // past its last LDS read only if the caller synchronises afterwards.
@@ -537,6 +582,9 @@ __device__ __forceinline__ void resident_group(const Mfma32Params& P, uint64_t g
     for (uint32_t s = 0; s < gi.nslots; ++s)
       mfma32_stage<L>(P, smem + s * P.slot_bytes, slot_gp(gi, s), b_product(P, slot_gp(gi, s), slot_li(gi, s)),
                       P.mods[slot_li(gi, s)], gi.v_lo);
+  } else if (P.n >= 1024) {
+    stage_uniform<L>(P, gi, smem);
+    stage_zero_fill<L>(P, gi, smem);
   } else {
     // all loads of a pass are issued before any is converted
     const uint32_t nitems = gi.nslots * (P.n >> 1);
@@ -557,7 +605,7 @@ __device__ __forceinline__ void resident_group(const Mfma32Params& P, uint64_t g
     stage_zero_fill<L>(P, gi, smem);
   }
   __syncthreads();
-  const uint64_t unit = grp * 4 + (threadIdx.x >> 6);
+  const uint64_t unit = grp * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (unit >= total_units) return;
   const uint64_t prod = unit >> P.log2U;
   const uint32_t tile = (uint32_t)(unit & (U - 1));
@@ -580,26 +628,10 @@ __device__ __forceinline__ void resident_group_split(const Mfma32Params& P, uint
   const uint32_t grp = item / P.kparts, part = item - grp * P.kparts;
   const uint32_t U = 1u << P.log2U;
   const GroupInfo gi = group_info(P, grp);
-  {
-    const uint32_t nitems = gi.nslots * (P.n >> 1);
-    for (uint32_t base = 0; base < nitems; base += kPrefetch * kThreads) {
-      uint4 pf[kPrefetch];
-#pragma unroll
-      for (int k = 0; k < kPrefetch; ++k) {
-        const uint32_t i = base + threadIdx.x + k * kThreads;
-        const uint4* src = i < nitems ? item_src(P, gi, i) : nullptr;
-        pf[k] = src ? *src : make_uint4(0, 0, 0, 0);
-      }
-#pragma unroll
-      for (int k = 0; k < kPrefetch; ++k) {
-        const uint32_t i = base + threadIdx.x + k * kThreads;
-        if (i < nitems) item_store<L>(P, gi, smem, i, pf[k]);
-      }
-    }
-    stage_zero_fill<L>(P, gi, smem);
-  }
+  stage_uniform<L>(P, gi, smem);  // split groups have n >= 2048
+  stage_zero_fill<L>(P, gi, smem);
   __syncthreads();
-  const uint32_t wave = threadIdx.x >> 6;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint64_t unit = (uint64_t)grp * 4 + wave;
   const uint64_t prod = unit >> P.log2U;
   const uint32_t tile = (uint32_t)(unit & (U - 1));
