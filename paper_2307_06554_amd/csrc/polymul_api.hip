@@ -398,7 +398,8 @@ polymul_status fill_stream(StreamParams& P, const void* a, const void* b, void* 
   P.ublocks = (P.r + 63) / 64;
   P.dc = P.r < 16 ? P.r : 16;
   P.nchunks = P.r / P.dc;
-  const uint32_t kflush = L <= 4 ? 16384u : 8192u;  // K values per exact int32 class sum
+  // a class sum holds at most L limb pairs of |product| <= 2^14: exact in int32 for K < 2^17 / L
+  const uint32_t kflush = (1u << 17) / (uint32_t)L - 1;
   const uint32_t fe = kflush / (P.dc * P.t);
   P.flush_every = fe < 1 ? 1 : fe;
   P.a_win = ((P.dc - 1) * P.t + 32 * P.tz + P.rowlen + 4 + 15) & ~15u;

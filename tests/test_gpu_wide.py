@@ -54,9 +54,10 @@ def test_u64_noncanonical_and_edges():
     _check64(full, full, GOLD)
 
 
-@pytest.mark.parametrize("n", [8192, 16384])
+@pytest.mark.parametrize("n", [8192, 16384, 32768])
 def test_u64_streaming_kchunks(n):
-    """Several K-chunks, at least one int32 flush between them."""
+    """Several K-chunks of 1024; from n = 16384 on (16 chunks, a flush every 15)
+    at least one int32 flush between them."""
     rng = np.random.Generator(np.random.PCG64(n))
     _check64(_rand64(rng, (2, n), GOLD), _rand64(rng, (2, n), GOLD), GOLD)
 
@@ -107,8 +108,8 @@ def test_workload4_goldilocks_full_size_sampled():
     jidx = rng.integers(0, n, size=pidx.size).astype(np.uint64)
     jidx[::8] = 0
     jidx[1::8] = n - 1
-    jidx[2::8] = 8191     # last coefficient of the first K-split window
-    jidx[3::8] = 8192
+    jidx[2::8] = 15359    # either side of the first flush's K range (15 chunks of 1024)
+    jidx[3::8] = 15360
     want = oracle.negacyclic_sample(w.a, w.b, w.q, pidx, jidx)
     have = got[pidx.astype(np.int64), jidx.astype(np.int64)]
     assert np.array_equal(have, want), mismatch_report(have, want)

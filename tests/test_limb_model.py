@@ -63,4 +63,5 @@ def test_kchunk_split_bound_goldilocks():
     want = oracle.negacyclic(np.array([a], dtype=np.uint64), np.array([b], dtype=np.uint64), q)[0]
     assert c_full == c_split == [int(v) for v in want]
     assert worst_split <= worst_full
-    assert 8 * 8192 * 2 ** 14 < 2 ** 31 <= 8 * 65536 * 2 ** 14
+    assert 8 * 16383 * 2 ** 14 < 2 ** 31 <= 8 * 16384 * 2 ** 14
+    assert 4 * 32767 * 2 ** 14 < 2 ** 31 <= 4 * 32768 * 2 ** 14
