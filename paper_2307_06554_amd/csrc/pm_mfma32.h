@@ -245,9 +245,10 @@ __device__ __forceinline__ void mfma_step(v16i (&acc)[2 * L - 1], const v4i (&a)
   }
 }
 
-// The same K-step with the A fragments double-buffered: after column L-2 the
-// next step's runs (read one step earlier) are aligned into `an` and the runs of
-// the step after that are read, so the next step starts straight with MFMAs.
+// The same K-step with the A fragments double-buffered: with column j, limb j
+// of the next step's runs (read one step earlier) is aligned into `an` and the
+// limb's runs of the step after that are read, so the next step starts
+// straight with MFMAs and at most a few LDS reads are in flight at a time.
 template <int L>
 __device__ __forceinline__ void mfma_step_pp(v16i (&acc)[2 * L - 1], const v4i (&a)[L], v4i (&an)[L],
                                              uint32_t (&araw)[L][5], uint32_t sh_next, const uint8_t* aplane,
@@ -259,25 +260,20 @@ __device__ __forceinline__ void mfma_step_pp(v16i (&acc)[2 * L - 1], const v4i (
     for (int i = 0; i < L; ++i)
       acc[i + j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], b[j], acc[i + j], 0, 0, 0);
     b[j] = *(const v4i*)(bplane + j * b_plane + boff_next);
-    if (j == (L >= 2 ? L - 2 : 0)) {
-      // limb by limb: align, then re-read the freed raw registers; interleaved
-      // with this column's MFMAs (one MFMA, four aligns, three LDS reads)
+    // limb j of the next step's A: align the runs read a step earlier, then re-read
+    // the freed raw registers (spread over the columns to keep few LDS reads in flight)
+    an[j][0] = (int)__builtin_amdgcn_alignbyte(araw[j][1], araw[j][0], sh_next);
+    an[j][1] = (int)__builtin_amdgcn_alignbyte(araw[j][2], araw[j][1], sh_next);
+    an[j][2] = (int)__builtin_amdgcn_alignbyte(araw[j][3], araw[j][2], sh_next);
+    an[j][3] = (int)__builtin_amdgcn_alignbyte(araw[j][4], araw[j][3], sh_next);
+    const uint32_t* p = (const uint32_t*)(aplane + j * a_plane) + (S_after >> 2);
 #pragma unroll
-      for (int i = 0; i < L; ++i) {
-        an[i][0] = (int)__builtin_amdgcn_alignbyte(araw[i][1], araw[i][0], sh_next);
-        an[i][1] = (int)__builtin_amdgcn_alignbyte(araw[i][2], araw[i][1], sh_next);
-        an[i][2] = (int)__builtin_amdgcn_alignbyte(araw[i][3], araw[i][2], sh_next);
-        an[i][3] = (int)__builtin_amdgcn_alignbyte(araw[i][4], araw[i][3], sh_next);
-        const uint32_t* p = (const uint32_t*)(aplane + i * a_plane) + (S_after >> 2);
+    for (int k = 0; k < 5; ++k) araw[j][k] = p[k];
 #pragma unroll
-        for (int k = 0; k < 5; ++k) araw[i][k] = p[k];
-      }
-#pragma unroll
-      for (int i = 0; i < L; ++i) {
-        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-        __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);
-        __builtin_amdgcn_sched_group_barrier(0x100, 3, 0);
-      }
+    for (int i = 0; i < L; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x002, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
     }
     __builtin_amdgcn_sched_barrier(0);
   }
