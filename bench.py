@@ -119,7 +119,13 @@ def other_workloads(steps, warmup):
     c = torch.empty_like(a)
     ms = time_steps(lambda: pm.polymul_negacyclic_u64(a, b, w.q, out=c), max(2, steps // 20), 2)
     ops = 2 * 64 * w.n * w.n * a.shape[0]
-    out[w.name] = {"polymuls_per_s": a.shape[0] / ms * 1e3, "ms_per_step": ms, "int8_tops": ops / ms / 1e9}
+    ws = torch.empty(pm.polymul_karatsuba_u64_workspace_size(w.n, a.shape[0], 3), dtype=torch.uint8, device=dev)
+    ck = torch.empty_like(a)
+    msk = time_steps(lambda: pm.polymul_negacyclic_u64_karatsuba(a, b, w.q, 3, workspace=ws, out=ck),
+                     max(2, steps // 20), 2)
+    out[w.name] = {"polymuls_per_s": a.shape[0] / ms * 1e3, "ms_per_step": ms, "int8_tops": ops / ms / 1e9,
+                   "karatsuba_depth3_polymuls_per_s": a.shape[0] / msk * 1e3, "karatsuba_ms_per_step": msk,
+                   "karatsuba_bit_identical": bool(torch.equal(c, ck))}
     return out
 
 

@@ -206,6 +206,18 @@ polymul_status polymul_negacyclic_u64_shared(const uint64_t* a, const uint64_t* 
  */
 polymul_status polymul_karatsuba_workspace_size(uint64_t n, uint32_t L, uint64_t batch,
                                                 uint32_t depth, uint64_t* bytes);
+/*
+ * The same route for 64-bit words and one modulus q < 2^64 (a, b, c as for
+ * polymul_negacyclic_u64): the sub-products run on the K-streaming kernel.
+ * Workspace rules and errors as above, sized by
+ * polymul_karatsuba_u64_workspace_size.
+ */
+polymul_status polymul_karatsuba_u64_workspace_size(uint64_t n, uint64_t batch, uint32_t depth,
+                                                    uint64_t* bytes);
+polymul_status polymul_negacyclic_u64_karatsuba(const uint64_t* a, const uint64_t* b, uint64_t* c,
+                                                uint64_t n, uint64_t q, uint64_t batch,
+                                                uint32_t depth, void* workspace,
+                                                uint64_t workspace_bytes, hipStream_t stream);
 polymul_status polymul_negacyclic_rns_karatsuba(const uint32_t* a, const uint32_t* b, uint32_t* c,
                                                 uint64_t n, const uint32_t* q, uint32_t L,
                                                 uint64_t batch, uint32_t depth, void* workspace,

@@ -11,6 +11,7 @@ from .binding import (  # noqa: F401
     polymul_crt_moduli,
     polymul_cyclic_u64,
     load_library,
+    polymul_karatsuba_u64_workspace_size,
     polymul_karatsuba_workspace_size,
     polymul_negacyclic,
     polymul_negacyclic_crt,
@@ -22,6 +23,7 @@ from .binding import (  # noqa: F401
     polymul_negacyclic_shared,
     polymul_negacyclic_u64_shared,
     polymul_negacyclic_u64,
+    polymul_negacyclic_u64_karatsuba,
     polymul_plan_create,
     polymul_plan_destroy,
     polymul_plan_execute,

@@ -37,6 +37,8 @@ _SIGNATURES = {
     "polymul_negacyclic_shared": (ctypes.c_int, [_vp, _vp, _vp, _u64, _u32, _u64, _vp]),
     "polymul_negacyclic_rns_shared": (ctypes.c_int, [_vp, _vp, _vp, _u64, _vp, _u32, _u64, _vp]),
     "polymul_negacyclic_u64_shared": (ctypes.c_int, [_vp, _vp, _vp, _u64, _u64, _u64, _vp]),
+    "polymul_karatsuba_u64_workspace_size": (ctypes.c_int, [_u64, _u64, _u32, ctypes.POINTER(_u64)]),
+    "polymul_negacyclic_u64_karatsuba": (ctypes.c_int, [_vp, _vp, _vp, _u64, _u64, _u64, _u32, _vp, _u64, _vp]),
     "polymul_karatsuba_workspace_size": (ctypes.c_int, [_u64, _u32, _u64, _u32, ctypes.POINTER(_u64)]),
     "polymul_negacyclic_rns_karatsuba": (ctypes.c_int, [_vp, _vp, _vp, _u64, _vp, _u32, _u64, _u32, _vp, _u64,
                                                         _vp]),
@@ -286,6 +288,32 @@ def polymul_negacyclic_rns_karatsuba(a, b, qs, depth, workspace=None, out=None, 
         _words(a, 4, "a"), _words(b, 4, "b"), _words(c, 4, "out"), n, ctypes.cast(qarr, ctypes.c_void_p), L,
         batch, int(depth), ctypes.c_void_p(workspace.data_ptr()), ws_bytes, _stream(stream))
     _check(st, "polymul_negacyclic_rns_karatsuba")
+    return c
+
+
+def polymul_karatsuba_u64_workspace_size(n, batch, depth):
+    """Bytes of device workspace polymul_negacyclic_u64_karatsuba needs."""
+    out = ctypes.c_uint64()
+    _check(load_library().polymul_karatsuba_u64_workspace_size(int(n), int(batch), int(depth), ctypes.byref(out)),
+           "polymul_karatsuba_u64_workspace_size")
+    return out.value
+
+
+def polymul_negacyclic_u64_karatsuba(a, b, q, depth, workspace=None, out=None, stream=None):
+    """polymul_negacyclic_u64 through `depth` Karatsuba levels (64-bit words [..., n])."""
+    import torch
+    if a.shape != b.shape or a.dim() < 1:
+        raise ValueError("a and b must have the same shape [..., n]")
+    n = a.shape[-1]
+    batch = a.numel() // n if n else 0
+    c = torch.empty_like(a) if out is None else out
+    need = polymul_karatsuba_u64_workspace_size(n, batch, depth)
+    if workspace is None:
+        workspace = torch.empty(max(need, 16), dtype=torch.uint8, device=a.device)
+    st = load_library().polymul_negacyclic_u64_karatsuba(
+        _words(a, 8, "a"), _words(b, 8, "b"), _words(c, 8, "out"), n, int(q), batch, int(depth),
+        ctypes.c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size(), _stream(stream))
+    _check(st, "polymul_negacyclic_u64_karatsuba")
     return c
 
 

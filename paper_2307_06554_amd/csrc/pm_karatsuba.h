@@ -14,22 +14,28 @@
 // previous block (z times a block shifts it by one; at i = 0 the negacyclic
 // wrap brings -P[n'-1]), level by level.
 #pragma once
+#include <type_traits>
 #include "pm_common.h"
+#include "pm_wide.h"
 
 namespace pm {
 
-struct KaraParams {
-  const uint32_t* a;
-  const uint32_t* b;
-  uint32_t* c;
-  uint32_t* sa;   // [nprod][3^k][n'] sub-operands of a
-  uint32_t* sb;   // same for b
-  const uint32_t* sc;  // [nprod][3^k][n'] sub-products
+// W: 32-bit words with up to 16 moduli (RNS channels), or 64-bit words with one.
+template <typename W, typename Mod, int NM>
+struct KaraParamsT {
+  const W* a;
+  const W* b;
+  W* c;
+  W* sa;   // [nprod][3^k][n'] sub-operands of a
+  W* sb;   // same for b
+  const W* sc;  // [nprod][3^k][n'] sub-products
   uint64_t nprod;
   uint32_t n, np, depth, nsub;  // n' = n >> depth, nsub = 3^depth
   uint32_t L;                   // moduli: product p uses mods[p % L]
-  ModQ32 mods[16];
+  Mod mods[NM];
 };
+typedef KaraParamsT<uint32_t, ModQ32, 16> KaraParams;
+typedef KaraParamsT<uint64_t, ModQ64, 1> KaraParams64;
 
 __device__ __forceinline__ uint32_t addq(uint32_t x, uint32_t y, uint32_t q) {
   const uint64_t s = (uint64_t)x + y;
@@ -38,45 +44,50 @@ __device__ __forceinline__ uint32_t addq(uint32_t x, uint32_t y, uint32_t q) {
 __device__ __forceinline__ uint32_t subq(uint32_t x, uint32_t y, uint32_t q) {
   return x >= y ? x - y : (uint32_t)((uint64_t)x + q - y);
 }
+__device__ __forceinline__ uint64_t addq(uint64_t x, uint64_t y, uint64_t q) { return addmod64(x, y, q); }
+__device__ __forceinline__ uint64_t subq(uint64_t x, uint64_t y, uint64_t q) { return submod64(x, y, q); }
+__device__ __forceinline__ uint32_t kara_reduce(uint32_t x, const ModQ32& m) { return reduce_u32(x, m); }
+__device__ __forceinline__ uint64_t kara_reduce(uint64_t x, const ModQ64& m) { return x < m.q ? x : mod_u64(x, m); }
 
 // One thread per (product, column i): reads x[2^k i .. 2^k i + 2^k) of a and b,
 // writes column i of every sub-operand.
-template <int K>
-__global__ __launch_bounds__(256) void kara_split_kernel(const KaraParams P) {
+template <int K, typename KP>
+__global__ __launch_bounds__(256) void kara_split_kernel(const KP P) {
+  typedef typename std::remove_const<typename std::remove_pointer<decltype(P.a)>::type>::type W;
   const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t p = gid / P.np;
   const uint32_t i = (uint32_t)(gid - p * P.np);
   if (p >= P.nprod) return;
-  const ModQ32& m = P.mods[p % P.L];
+  const auto& m = P.mods[p % P.L];
   constexpr int R = 1 << K;
   int nsub = 1;
   for (int l = 0; l < K; ++l) nsub *= 3;
 #pragma unroll
   for (int op = 0; op < 2; ++op) {
-    const uint32_t* X = (op == 0 ? P.a : P.b) + p * P.n + (uint64_t)R * i;
-    uint32_t* S = (op == 0 ? P.sa : P.sb) + p * (uint64_t)nsub * P.np + i;
-    uint32_t x[R];
+    const W* X = (op == 0 ? P.a : P.b) + p * P.n + (uint64_t)R * i;
+    W* S = (op == 0 ? P.sa : P.sb) + p * (uint64_t)nsub * P.np + i;
+    W x[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) x[r] = reduce_u32(X[r], m);
+    for (int r = 0; r < R; ++r) x[r] = kara_reduce(X[r], m);
     // level by level: v holds, for every choice prefix, the 2^(K-l) partial sums still split by the deeper bits
-    uint32_t v[R * 27 / 8 + 1];  // enough for 3^K values at the end (K <= 3)
+    W v[R * 27 / 8 + 1];  // enough for 3^K values at the end (K <= 3)
 #pragma unroll
     for (int r = 0; r < R; ++r) v[r] = x[r];
     int cnt = 1, width = R;  // cnt prefixes, each with `width` values (indexed by the remaining bits)
 #pragma unroll
     for (int l = 0; l < K; ++l) {
       // split on bit 0 of the remaining index: even part, odd part, their sum
-      uint32_t nv[R * 27 / 8 + 1];
+      W nv[R * 27 / 8 + 1];
       const int hw = width / 2;
 #pragma unroll
       for (int c0 = 0; c0 < cnt; ++c0)
 #pragma unroll
         for (int h = 0; h < hw; ++h) {
-          const uint32_t e = v[c0 * width + 2 * h], o = v[c0 * width + 2 * h + 1];
+          const W e = v[c0 * width + 2 * h], o = v[c0 * width + 2 * h + 1];
           // new prefix index d_l * cnt + c0 keeps s = d_1 + 3 d_2 + ... ordering
           nv[(0 * cnt + c0) * hw + h] = e;
           nv[(1 * cnt + c0) * hw + h] = o;
-          nv[(2 * cnt + c0) * hw + h] = addq(e, o, m.q);
+          nv[(2 * cnt + c0) * hw + h] = addq(e, o, (W)m.q);
         }
       cnt *= 3;
       width = hw;
@@ -89,42 +100,43 @@ __global__ __launch_bounds__(256) void kara_split_kernel(const KaraParams P) {
 }
 
 // One thread per (product, column i): c[2^k i + r] for r < 2^k.
-template <int K>
-__global__ __launch_bounds__(256) void kara_combine_kernel(const KaraParams P) {
+template <int K, typename KP>
+__global__ __launch_bounds__(256) void kara_combine_kernel(const KP P) {
+  typedef typename std::remove_const<typename std::remove_pointer<decltype(P.a)>::type>::type W;
   const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t p = gid / P.np;
   const uint32_t i = (uint32_t)(gid - p * P.np);
   if (p >= P.nprod) return;
-  const uint32_t q = P.mods[p % P.L].q;
+  const W q = (W)P.mods[p % P.L].q;
   constexpr int NS = K == 1 ? 3 : K == 2 ? 9 : 27;
-  const uint32_t* S = P.sc + p * (uint64_t)NS * P.np;
+  const W* S = P.sc + p * (uint64_t)NS * P.np;
   // blocks: cur[s][j] (block of size B per sub-product), prev[s] = last element of the previous block
-  uint32_t cur[NS * 1];
-  uint32_t prv[NS];
+  W cur[NS * 1];
+  W prv[NS];
   const uint32_t ip = i ? i - 1 : P.np - 1;
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     cur[s] = S[(uint64_t)s * P.np + i];
-    const uint32_t pv = S[(uint64_t)s * P.np + ip];
-    prv[s] = i ? pv : (pv ? q - pv : 0u);  // z^(n') = -1 at the deepest level
+    const W pv = S[(uint64_t)s * P.np + ip];
+    prv[s] = i ? pv : (pv ? q - pv : (W)0);  // z^(n') = -1 at the deepest level
   }
   // combine the deepest level first: children differ in the most significant choice digit
-  uint32_t blk[1 << K][NS];  // blk[j][parent] values; starts with B = 1
-  uint32_t pl[NS];
+  W blk[1 << K][NS];  // blk[j][parent] values; starts with B = 1
+  W pl[NS];
   int count = NS, B = 1;
 #pragma unroll
   for (int s = 0; s < NS; ++s) { blk[0][s] = cur[s]; pl[s] = prv[s]; }
 #pragma unroll
   for (int l = K; l >= 1; --l) {
     const int parents = count / 3;  // children of parent x: x + parents * d, d = 0, 1, 2
-    uint32_t nb[1 << K][NS];
-    uint32_t npl[NS];
+    W nb[1 << K][NS];
+    W npl[NS];
 #pragma unroll
     for (int x = 0; x < parents; ++x) {
       const int c0 = x, c1 = x + parents, c2 = x + 2 * parents;
 #pragma unroll
       for (int j = 0; j < B; ++j) {
-        const uint32_t s1 = j ? blk[j - 1][c1] : pl[c1];  // (z * P1)[j]
+        const W s1 = j ? blk[j - 1][c1] : pl[c1];  // (z * P1)[j]
         nb[2 * j][x] = addq(blk[j][c0], s1, q);
         nb[2 * j + 1][x] = subq(subq(blk[j][c2], blk[j][c0], q), blk[j][c1], q);
       }
@@ -139,7 +151,7 @@ __global__ __launch_bounds__(256) void kara_combine_kernel(const KaraParams P) {
 #pragma unroll
     for (int x = 0; x < count; ++x) pl[x] = npl[x];
   }
-  uint32_t* C = P.c + p * P.n + ((uint64_t)i << K);
+  W* C = P.c + p * P.n + ((uint64_t)i << K);
 #pragma unroll
   for (int r = 0; r < (1 << K); ++r) C[r] = blk[r][0];
 }

@@ -476,6 +476,37 @@ polymul_status run_mfma32(const uint32_t* a, const uint32_t* b, uint32_t* c, uin
   }
 }
 
+// ---------------------------------------------------------------- Karatsuba
+template <typename KP>
+polymul_status kara_split(const KP& K, uint32_t depth, uint64_t blocks, hipStream_t s) {
+  switch (depth) {
+    case 1: hipLaunchKernelGGL((kara_split_kernel<1, KP>), dim3((uint32_t)blocks), dim3(256), 0, s, K); break;
+    case 2: hipLaunchKernelGGL((kara_split_kernel<2, KP>), dim3((uint32_t)blocks), dim3(256), 0, s, K); break;
+    default: hipLaunchKernelGGL((kara_split_kernel<3, KP>), dim3((uint32_t)blocks), dim3(256), 0, s, K); break;
+  }
+  return launch_status();
+}
+template <typename KP>
+polymul_status kara_combine(const KP& K, uint32_t depth, uint64_t blocks, hipStream_t s) {
+  switch (depth) {
+    case 1: hipLaunchKernelGGL((kara_combine_kernel<1, KP>), dim3((uint32_t)blocks), dim3(256), 0, s, K); break;
+    case 2: hipLaunchKernelGGL((kara_combine_kernel<2, KP>), dim3((uint32_t)blocks), dim3(256), 0, s, K); break;
+    default: hipLaunchKernelGGL((kara_combine_kernel<3, KP>), dim3((uint32_t)blocks), dim3(256), 0, s, K); break;
+  }
+  return launch_status();
+}
+
+// Workspace bytes of one Karatsuba call: sub-operands of a and b and the sub-products.
+polymul_status kara_workspace(uint64_t n, uint64_t products, uint32_t depth, uint32_t word, uint64_t* bytes) {
+  if (!bytes || depth < 1 || depth > 3 || !is_pow2(n) || n > 65536 || (n >> depth) < 4) return POLYMUL_EINVAL;
+  uint64_t nsub = 1;
+  for (uint32_t l = 0; l < depth; ++l) nsub *= 3;
+  const unsigned __int128 words = (unsigned __int128)products * nsub * (n >> depth);
+  if (words >> 57) return POLYMUL_EINVAL;
+  *bytes = (uint64_t)(3 * words * word);
+  return POLYMUL_OK;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------- plans
@@ -893,14 +924,46 @@ polymul_status polymul_negacyclic_u64_shared(const uint64_t* a, const uint64_t* 
 
 polymul_status polymul_karatsuba_workspace_size(uint64_t n, uint32_t L, uint64_t batch, uint32_t depth,
                                                 uint64_t* bytes) {
-  if (!bytes || depth < 1 || depth > 3 || L < 1 || L > 16 || !is_pow2(n) || n > 65536 || (n >> depth) < 4)
-    return POLYMUL_EINVAL;
-  uint64_t nsub = 1;
-  for (uint32_t l = 0; l < depth; ++l) nsub *= 3;
-  const unsigned __int128 words = (unsigned __int128)batch * L * nsub * (n >> depth);
-  if (words >> 58) return POLYMUL_EINVAL;
-  *bytes = (uint64_t)(3 * words * 4);
-  return POLYMUL_OK;
+  if (L < 1 || L > 16) return POLYMUL_EINVAL;
+  return kara_workspace(n, batch * L, depth, 4, bytes);
+}
+
+polymul_status polymul_karatsuba_u64_workspace_size(uint64_t n, uint64_t batch, uint32_t depth, uint64_t* bytes) {
+  return kara_workspace(n, batch, depth, 8, bytes);
+}
+
+polymul_status polymul_negacyclic_u64_karatsuba(const uint64_t* a, const uint64_t* b, uint64_t* c, uint64_t n,
+                                                uint64_t q, uint64_t batch, uint32_t depth, void* workspace,
+                                                uint64_t workspace_bytes, hipStream_t stream) {
+  if (q < 2) return POLYMUL_EINVAL;
+  uint64_t need;
+  polymul_status st = kara_workspace(n, batch, depth, 8, &need);
+  if (st != POLYMUL_OK) return st;
+  uint64_t bytes;
+  st = check_arrays(a, b, c, n, batch, 1, 8, &bytes);
+  if (st != POLYMUL_OK || batch == 0) return st;
+  if (!workspace || ((uintptr_t)workspace & 15) || workspace_bytes < need) return POLYMUL_EINVAL;
+  if (overlaps(workspace, need, a, bytes) || overlaps(workspace, need, b, bytes) || overlaps(workspace, need, c, bytes))
+    return POLYMUL_EALIAS;
+  const uint32_t nsub = depth == 1 ? 3 : depth == 2 ? 9 : 27;
+  const uint32_t np = (uint32_t)(n >> depth);
+  const uint64_t sub_words = batch * nsub * np;
+  KaraParams64 K{};
+  K.a = a; K.b = b; K.c = c;
+  K.sa = (uint64_t*)workspace;
+  K.sb = K.sa + sub_words;
+  uint64_t* sc = K.sb + sub_words;
+  K.sc = sc;
+  K.nprod = batch; K.n = (uint32_t)n; K.np = np; K.depth = depth; K.nsub = nsub; K.L = 1;
+  K.mods[0] = make_mod64(q, limbs64(&q, 1));
+  const uint64_t blocks = (batch * np + 255) / 256;
+  if (blocks > 0x7FFFFFFFull) return POLYMUL_EUNSUPPORTED;
+  st = kara_split(K, depth, blocks, stream);
+  if (st != POLYMUL_OK) return st;
+  // the sub-products: batch * nsub products of degree bound n' (K-streamed, 64-bit words)
+  st = run_stream<uint64_t>(K.sa, K.sb, sc, np, &q, 1, 1, 0, batch * nsub, stream, false, nsub);
+  if (st != POLYMUL_OK) return st;
+  return kara_combine(K, depth, blocks, stream);
 }
 
 polymul_status polymul_negacyclic_rns_karatsuba(const uint32_t* a, const uint32_t* b, uint32_t* c, uint64_t n,
@@ -934,22 +997,12 @@ polymul_status polymul_negacyclic_rns_karatsuba(const uint32_t* a, const uint32_
   const uint64_t threads = nprod * np;
   const uint64_t blocks = (threads + 255) / 256;
   if (blocks > 0x7FFFFFFFull) return POLYMUL_EUNSUPPORTED;
-  switch (depth) {
-    case 1: hipLaunchKernelGGL(kara_split_kernel<1>, dim3((uint32_t)blocks), dim3(256), 0, stream, K); break;
-    case 2: hipLaunchKernelGGL(kara_split_kernel<2>, dim3((uint32_t)blocks), dim3(256), 0, stream, K); break;
-    default: hipLaunchKernelGGL(kara_split_kernel<3>, dim3((uint32_t)blocks), dim3(256), 0, stream, K); break;
-  }
-  st = launch_status();
+  st = kara_split(K, depth, blocks, stream);
   if (st != POLYMUL_OK) return st;
   // the sub-products: nprod * nsub products of degree bound n' with modulus (i / nsub) % L
   st = run_mfma32(K.sa, K.sb, sc, np, q, L, L, 0, nprod * nsub, stream, false, nsub);
   if (st != POLYMUL_OK) return st;
-  switch (depth) {
-    case 1: hipLaunchKernelGGL(kara_combine_kernel<1>, dim3((uint32_t)blocks), dim3(256), 0, stream, K); break;
-    case 2: hipLaunchKernelGGL(kara_combine_kernel<2>, dim3((uint32_t)blocks), dim3(256), 0, stream, K); break;
-    default: hipLaunchKernelGGL(kara_combine_kernel<3>, dim3((uint32_t)blocks), dim3(256), 0, stream, K); break;
-  }
-  return launch_status();
+  return kara_combine(K, depth, blocks, stream);
 }
 
 polymul_status polymul_tune_set(uint64_t n, uint32_t L, uint32_t t) {

@@ -211,3 +211,18 @@ def test_crt_arguments():
     assert call("polymul_crt_moduli", 100, 17, out, ctypes.byref(cnt)) == EINVAL
     assert call("polymul_crt_moduli", 256, 17, None, ctypes.byref(cnt)) == EINVAL
     assert call("polymul_crt_moduli", 65536, 0xFFFFFFFF, out, ctypes.byref(cnt)) == 0 and cnt.value <= 11
+
+
+def test_karatsuba_u64_arguments():
+    assert pm.polymul_karatsuba_u64_workspace_size(65536, 16, 2) == 3 * 8 * 16 * 9 * 16384
+    with pytest.raises(pm.PolymulError):
+        pm.polymul_karatsuba_u64_workspace_size(65536, 16, 4)
+    W = 0x40000000
+    need = pm.polymul_karatsuba_u64_workspace_size(256, 1, 1)
+    k = "polymul_negacyclic_u64_karatsuba"
+    assert call(k, A, B, C, 256, 17, 1, 1, W, need - 1, None) == EINVAL
+    assert call(k, A, B, C, 256, 1, 1, 1, W, need, None) == EINVAL
+    assert call(k, A, B, C, 256, 17, 1, 0, W, need, None) == EINVAL
+    assert call(k, A, B, A, 256, 17, 1, 1, W, need, None) == EALIAS
+    assert call(k, A, B, C, 256, 17, 1, 1, B + 16, need, None) == EALIAS
+    assert call(k, None, None, None, 256, 17, 0, 1, None, 0, None) == 0

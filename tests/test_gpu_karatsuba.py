@@ -116,3 +116,34 @@ def test_karatsuba_empty_batch():
     a = torch.empty((0, 1, 64), dtype=torch.int32, device="cuda:0")
     c = pm.polymul_negacyclic_rns_karatsuba(a, a.clone(), qs, 2)
     assert c.shape == (0, 1, 64)
+
+
+@pytest.mark.parametrize("depth", [1, 2, 3])
+@pytest.mark.parametrize("n,q", [(64, inputs.GOLDILOCKS), (1024, (1 << 64) - 59), (8192, inputs.GOLDILOCKS),
+                                 (512, 1 << 40), (256, 3329)])
+def test_karatsuba_u64_matches_oracle(depth, n, q):
+    rng = np.random.Generator(np.random.PCG64(n * 3 + depth))
+    a = rng.integers(0, q, size=(2, n), dtype=np.uint64)
+    b = rng.integers(0, q, size=(2, n), dtype=np.uint64)
+    got = to_host(pm.polymul_negacyclic_u64_karatsuba(to_dev(a), to_dev(b), q, depth), np.uint64)
+    want = oracle.negacyclic(a, b, q)
+    assert np.array_equal(got, want), mismatch_report(got, want)
+
+
+def test_karatsuba_u64_goldilocks_full_size_sampled():
+    # the n = 65536 Goldilocks workload through depth 2: sampled against the oracle, and
+    # word for word equal to the direct streaming route
+    w = inputs.make_workload(4)
+    da, db = to_dev(w.a), to_dev(w.b)
+    got = to_host(pm.polymul_negacyclic_u64_karatsuba(da, db, w.q, 2), np.uint64)
+    direct = to_host(pm.polymul_negacyclic_u64(da, db, w.q), np.uint64)
+    assert np.array_equal(got, direct), mismatch_report(got, direct)
+    B, n = w.a.shape
+    rng = np.random.Generator(np.random.PCG64(41))
+    pidx = np.repeat(np.arange(B, dtype=np.uint64), 4)
+    jidx = rng.integers(0, n, size=pidx.size).astype(np.uint64)
+    jidx[::4] = 0
+    jidx[1::4] = n - 1
+    want = oracle.negacyclic_sample(w.a, w.b, w.q, pidx, jidx)
+    have = got[pidx.astype(np.int64), jidx.astype(np.int64)]
+    assert np.array_equal(have, want), mismatch_report(have, want)
