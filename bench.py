@@ -80,8 +80,15 @@ def cpu_baseline(w, budget_s):
     t0 = time.perf_counter()
     oracle.negacyclic_rns(w.a[:pairs], w.b[:pairs], w.qs)
     dt = time.perf_counter() - t0
+    # one thread on one product (one channel of one pair), for the per-core rate
+    prev = oracle.set_threads(1)
+    t1 = time.perf_counter()
+    oracle.negacyclic(w.a[:1, 0], w.b[:1, 0], w.qs[0])
+    dt1 = time.perf_counter() - t1
+    oracle.set_threads(prev)
     return {"value": pairs * L / dt, "unit": "polymuls/s", "cores": cores, "kind": "oracle",
-            "sample": f"{pairs} of {B} ciphertext pairs x {L} channels (n={n}, 30-bit q), {dt:.1f} s wall"}
+            "sample": f"{pairs} of {B} ciphertext pairs x {L} channels (n={n}, 30-bit q), {dt:.1f} s wall",
+            "single_thread_value": 1 / dt1}
 
 
 def other_workloads(steps, warmup):

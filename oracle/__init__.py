@@ -47,6 +47,8 @@ def _load():
     lib.oracle_negacyclic_u64_sample.argtypes = [vp, vp, u64, u64, vp, vp, u64, vp]
     lib.oracle_cyclic_u32.argtypes = [vp, vp, vp, u64, u32, u64]
     lib.oracle_cyclic_u64.argtypes = [vp, vp, vp, u64, u64, u64]
+    lib.oracle_set_threads.argtypes = [ctypes.c_int]
+    lib.oracle_set_threads.restype = ctypes.c_int
     for f in (lib.oracle_negacyclic_u32, lib.oracle_negacyclic_u64, lib.oracle_negacyclic_rns_u32,
               lib.oracle_negacyclic_u32_sample, lib.oracle_negacyclic_u64_sample, lib.oracle_cyclic_u32, lib.oracle_cyclic_u64):
         f.restype = ctypes.c_int
@@ -60,6 +62,11 @@ def _ptr(x):
 
 def _as(x, dtype):
     return np.ascontiguousarray(np.asarray(x).astype(dtype, copy=False))
+
+
+def set_threads(threads):
+    """OpenMP threads for the following calls (0 leaves it); returns the previous count."""
+    return _load().oracle_set_threads(int(threads))
 
 
 def negacyclic(a, b, q):

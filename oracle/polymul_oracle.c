@@ -29,6 +29,7 @@
  * there x^n = +1, so the folded terms are added instead of subtracted:
  *     c_j = ( sum_{i<=j} a_i b_{j-i} + sum_{i>j} a_i b_{n+j-i} ) mod q.
  */
+#include <omp.h>
 #include <stdint.h>
 #include <stddef.h>
 
@@ -173,4 +174,12 @@ int oracle_negacyclic_u64_sample(const uint64_t* a, const uint64_t* b, uint64_t 
     for (int64_t s = 0; s < (int64_t)count; ++s)
         c_out[s] = coeff_u64(a + pidx[s] * n, b + pidx[s] * n, n, q, jidx[s] % n);
     return 0;
+}
+
+/* Threads the OpenMP loops above use from now on (a timing knob; results do not
+   depend on it).  Returns the previous count. */
+int oracle_set_threads(int threads) {
+    const int prev = omp_get_max_threads();
+    if (threads > 0) omp_set_num_threads(threads);
+    return prev;
 }
