@@ -19,7 +19,10 @@
 // int32 (2L-1 accumulator sets).  Bound: |digit product| <= 2^14 and at most L
 // pairs share a class, so |T_s| <= L * n * 2^14 < 2^31 for L*n <= 2^16 - 1;
 // the host only routes n <= 8192 here (L <= 4).  Recombination
-// c = sum_s T_s 2^(8s) mod q runs as Horner steps with Barrett reduction.
+// c = sum_s T_s 2^(8s) mod q is one signed 64-bit dot product of the T_s with the
+// centred residues of 2^(8s) when the host has shown it stays below 2^62, else
+// Horner steps; either way a Barrett reduction ends it.  In the cyclic ring
+// x^n - 1 (the `cyclic` flag) the wrapped terms keep their sign.
 #pragma once
 #include "pm_common.h"
 
@@ -279,9 +282,9 @@ __device__ __forceinline__ void mfma_step_pp(v16i (&acc)[2 * L - 1], const v4i (
   }
 }
 
-// One 32x32 output tile of one product: the whole K loop for all L*L limb pairs.
-// Per step: byte-align the A runs read during the previous step, issue the next
-// step's A reads into the freed raw registers, then the MFMAs (which refill B).
+// One 32x32 output tile of one product: the K loop (K-steps [st_lo, st_hi), all
+// of them by default) for all L*L limb pairs, two steps per iteration so that
+// the two A fragment sets swap roles without register copies.
 template <int L>
 __device__ __forceinline__ void mfma32_tile(const Mfma32Params& P, const uint8_t* aplane, const uint8_t* bplane,
                                             int z0, int u0, int v_lo, v16i (&acc)[2 * L - 1], int st_lo = 0,

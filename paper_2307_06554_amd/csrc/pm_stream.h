@@ -13,9 +13,11 @@
 // Accumulator bound (K-split): a shift class holds at most L limb pairs of
 // |product| <= 2^14, so its int32 sum is exact for K <= (2^31-1) / (L 2^14);
 // the host sets flush_every so that every flush covers at most 2^17 / L - 1 K
-// values (32767 for L = 4, 16383 for L = 8).  A flush folds sum_s T_s 2^(8s) into a running
-// residue mod q with 128-bit arithmetic (Sec. 2.4 limbs recombined, then the
-// modular reduction the paper leaves to Barrett/Montgomery, Sec. 2.6).
+// values (32767 for L = 4, 16383 for L = 8).  A flush folds sum_s T_s 2^(8s)
+// into a running residue mod q with 128-bit arithmetic (Sec. 2.4 limbs
+// recombined, then the modular reduction the paper leaves to Barrett /
+// Montgomery, Sec. 2.6).  In grouped plans a block's chunks can be cut into
+// runs on several workgroups (kparts), whose residues a second kernel adds.
 #pragma once
 #include "pm_common.h"
 #include "pm_wide.h"
