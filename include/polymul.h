@@ -210,9 +210,10 @@ polymul_status polymul_karatsuba_workspace_size(uint64_t n, uint32_t L, uint64_t
                                                 uint32_t depth, uint64_t* bytes);
 /*
  * The same route for 64-bit words and one modulus q < 2^64 (a, b, c as for
- * polymul_negacyclic_u64): the sub-products run on the K-streaming kernel.
- * Workspace rules and errors as above, sized by
- * polymul_karatsuba_u64_workspace_size.
+ * polymul_negacyclic_u64): the sub-products run on the K-streaming kernel,
+ * their K range cut into up to four runs when that fills the GPU's rounds of
+ * workgroups better.  Workspace rules and errors as above, sized by
+ * polymul_karatsuba_u64_workspace_size (room for the runs included).
  */
 polymul_status polymul_karatsuba_u64_workspace_size(uint64_t n, uint64_t batch, uint32_t depth,
                                                     uint64_t* bytes);

@@ -416,7 +416,7 @@ polymul_status fill_stream(StreamParams& P, const void* a, const void* b, void* 
 template <int L, typename W, int WPE>
 polymul_status launch_stream_L(const StreamParams& P, uint32_t lds, hipStream_t s) {
   if (allow_lds<k_stream<L, W, WPE>>() != POLYMUL_OK) return POLYMUL_EDEVICE;
-  const uint64_t blocks = P.nprod * P.ublocks;
+  const uint64_t blocks = P.nprod * P.ublocks * P.kparts;
   if (blocks > 0x7FFFFFFFull) return POLYMUL_EUNSUPPORTED;
   hipLaunchKernelGGL((stream_kernel<L, W, WPE>), dim3((uint32_t)blocks), dim3(kStreamThreads), lds, s, P);
   return launch_status();
@@ -496,15 +496,31 @@ polymul_status kara_combine(const KP& K, uint32_t depth, uint64_t blocks, hipStr
   return launch_status();
 }
 
-// Workspace bytes of one Karatsuba call: sub-operands of a and b and the sub-products.
-polymul_status kara_workspace(uint64_t n, uint64_t products, uint32_t depth, uint32_t word, uint64_t* bytes) {
+// Most K runs a streamed Karatsuba sub-product launch is cut into (whole rounds, see below).
+constexpr uint32_t kKaraRuns = 4;
+
+// Workspace bytes of one Karatsuba call: sub-operands of a and b and the sub-products
+// (3 words per sub-product coefficient), plus kKaraRuns copies of the sub-products for
+// runs when `runs` is set.
+polymul_status kara_workspace(uint64_t n, uint64_t products, uint32_t depth, uint32_t word, uint64_t* bytes,
+                              bool runs = false) {
   if (!bytes || depth < 1 || depth > 3 || !is_pow2(n) || n > 65536 || (n >> depth) < 4) return POLYMUL_EINVAL;
   uint64_t nsub = 1;
   for (uint32_t l = 0; l < depth; ++l) nsub *= 3;
   const unsigned __int128 words = (unsigned __int128)products * nsub * (n >> depth);
   if (words >> 57) return POLYMUL_EINVAL;
-  *bytes = (uint64_t)(3 * words * word);
+  *bytes = (uint64_t)((3 + (runs ? kKaraRuns : 0)) * words * word);
   return POLYMUL_OK;
+}
+
+// c = sum of the kparts runs' residues mod q, 64-bit words.
+__global__ __launch_bounds__(256) void split_sum64_kernel(const uint64_t* __restrict__ ws, uint64_t* __restrict__ c,
+                                                          uint64_t words, uint32_t kparts, uint64_t q) {
+  const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= words) return;
+  uint64_t acc = 0;
+  for (uint32_t p = 0; p < kparts; ++p) acc = addmod64(acc, ws[(uint64_t)p * words + i], q);
+  c[i] = acc;
 }
 
 }  // namespace
@@ -929,7 +945,7 @@ polymul_status polymul_karatsuba_workspace_size(uint64_t n, uint32_t L, uint64_t
 }
 
 polymul_status polymul_karatsuba_u64_workspace_size(uint64_t n, uint64_t batch, uint32_t depth, uint64_t* bytes) {
-  return kara_workspace(n, batch, depth, 8, bytes);
+  return kara_workspace(n, batch, depth, 8, bytes, true);
 }
 
 polymul_status polymul_negacyclic_u64_karatsuba(const uint64_t* a, const uint64_t* b, uint64_t* c, uint64_t n,
@@ -937,7 +953,7 @@ polymul_status polymul_negacyclic_u64_karatsuba(const uint64_t* a, const uint64_
                                                 uint64_t workspace_bytes, hipStream_t stream) {
   if (q < 2) return POLYMUL_EINVAL;
   uint64_t need;
-  polymul_status st = kara_workspace(n, batch, depth, 8, &need);
+  polymul_status st = kara_workspace(n, batch, depth, 8, &need, true);
   if (st != POLYMUL_OK) return st;
   uint64_t bytes;
   st = check_arrays(a, b, c, n, batch, 1, 8, &bytes);
@@ -960,9 +976,35 @@ polymul_status polymul_negacyclic_u64_karatsuba(const uint64_t* a, const uint64_
   if (blocks > 0x7FFFFFFFull) return POLYMUL_EUNSUPPORTED;
   st = kara_split(K, depth, blocks, stream);
   if (st != POLYMUL_OK) return st;
-  // the sub-products: batch * nsub products of degree bound n' (K-streamed, 64-bit words)
-  st = run_stream<uint64_t>(K.sa, K.sb, sc, np, &q, 1, 1, 0, batch * nsub, stream, false, nsub);
+  // the sub-products: batch * nsub products of degree bound n' (K-streamed, 64-bit words).
+  // The streaming kernel runs whole rounds of its workgroups (one per CU at 8 limbs,
+  // two at 4); when the blocks fill the last round poorly their K range is cut into
+  // runs, whose residues a second kernel adds, if that takes fewer rounds per block.
+  const int Ls = limbs64(&q, 1);
+  StreamParams SP;
+  uint32_t lds;
+  st = fill_stream(SP, K.sa, K.sb, sc, np, &q, 1, 1, 0, batch * nsub, Ls, &lds, false, nsub);
   if (st != POLYMUL_OK) return st;
+  const uint64_t sblocks = batch * nsub * SP.ublocks;
+  const uint64_t per_round = (uint64_t)device_cus() * (Ls == 4 ? 2 : 1);
+  uint32_t runs = 1;
+  double best = (double)((sblocks + per_round - 1) / per_round);
+  for (uint32_t k = 2; k <= kKaraRuns && k <= SP.nchunks; k *= 2) {
+    const double rounds = (double)((sblocks * k + per_round - 1) / per_round) / k;
+    if (rounds < best - 1e-9) { best = rounds; runs = k; }
+  }
+  if (runs > 1) {
+    SP.kparts = runs;
+    SP.part_ws = sc + sub_words;  // runs * sub_words words after the sub-products
+  }
+  st = Ls == 4 ? launch_stream_L<4, uint64_t, 2>(SP, lds, stream) : launch_stream_L<8, uint64_t, 1>(SP, lds, stream);
+  if (st != POLYMUL_OK) return st;
+  if (runs > 1) {
+    hipLaunchKernelGGL(split_sum64_kernel, dim3((uint32_t)((sub_words + 255) / 256)), dim3(256), 0, stream,
+                       (const uint64_t*)SP.part_ws, sc, sub_words, runs, q);
+    st = launch_status();
+    if (st != POLYMUL_OK) return st;
+  }
   return kara_combine(K, depth, blocks, stream);
 }
 

@@ -214,7 +214,8 @@ def test_crt_arguments():
 
 
 def test_karatsuba_u64_arguments():
-    assert pm.polymul_karatsuba_u64_workspace_size(65536, 16, 2) == 3 * 8 * 16 * 9 * 16384
+    # sub-operands of a and b, the sub-products and four copies of them for K runs
+    assert pm.polymul_karatsuba_u64_workspace_size(65536, 16, 2) == 7 * 8 * 16 * 9 * 16384
     with pytest.raises(pm.PolymulError):
         pm.polymul_karatsuba_u64_workspace_size(65536, 16, 4)
     W = 0x40000000
