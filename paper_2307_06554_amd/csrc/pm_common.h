@@ -76,14 +76,15 @@ __device__ __forceinline__ uint32_t reduce_u64(uint64_t x, const ModQ32& m) {
   if (r >= m.q) r -= m.q;
   return (uint32_t)r;
 }
-// x mod q for a 32-bit word: with m32 = floor(2^32/q) the estimate
-// floor(x*m32/2^32) is at most 2 below floor(x/q) and never above it.
+// x mod q for a 32-bit word.  With m32 = floor(2^32/q) >= 2^32/q - 1 and x < 2^32,
+// x*m32/2^32 > x/q - 1, so the estimate floor(x*m32/2^32) is floor(x/q) or one
+// less and r = x - estimate*q lies in [0, 2q) (and below 2^32: m32 = 1 when
+// q > 2^31).  One conditional subtraction ends it; min(r, r - q) is that
+// subtraction, r - q wrapping above r when r < q.
 __device__ __forceinline__ uint32_t reduce_u32(uint32_t x, const ModQ32& m) {
-  uint32_t qe = __umulhi(x, m.m32);
-  uint32_t r = x - qe * m.q;
-  if (r >= m.q) r -= m.q;
-  if (r >= m.q) r -= m.q;
-  return r;
+  const uint32_t qe = __umulhi(x, m.m32);
+  const uint32_t r = x - qe * m.q;
+  return min(r, r - m.q);
 }
 // Signed |x| < 2^62.
 __device__ __forceinline__ uint32_t reduce_i64(int64_t x, const ModQ32& m) {
@@ -101,6 +102,29 @@ __device__ __forceinline__ uint32_t digits32(uint32_t x, uint32_t q, uint32_t th
 template <int L>
 __device__ __forceinline__ uint32_t neg_digits32(uint32_t x, uint32_t q, uint32_t thr) {
   return digits32<L>(x == 0 ? 0u : q - x, q, thr);
+}
+// Both digit words of residues x in [0, q): of x and of a representative of -x.
+// When q <= thr (every modulus below the window's top, e.g. q < 2^31 for L = 4)
+// x and q - x are in the window as they are; q - 0 = q stands for 0.
+// Four residues at a time, the window test taken once.
+template <int L>
+__device__ __forceinline__ void digits_pm32(const uint32_t (&x)[4], uint32_t q, uint32_t thr, uint32_t (&pos)[4],
+                                            uint32_t (&neg)[4]) {
+  constexpr uint32_t B = (uint32_t)limb_bias(L);
+  if (q <= thr) {
+    const uint32_t qb = q + B;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      pos[k] = (x[k] + B) ^ B;
+      neg[k] = (qb - x[k]) ^ B;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      pos[k] = digits32<L>(x[k], q, thr);
+      neg[k] = neg_digits32<L>(x[k], q, thr);
+    }
+  }
 }
 
 }  // namespace pm

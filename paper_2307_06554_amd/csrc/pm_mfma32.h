@@ -65,14 +65,20 @@ struct Mfma32Params {
   int32_t rcent[kMaxQ][8];  // 2^(8s) mod q as a centred residue, s < 2L-1
 };
 
-// Byte i of each of the four digit words, packed into one word (byte k from w[k]).
+// Byte i of each of the four digit words, packed into one word (byte k from w[k]):
+// a 4x4 byte transpose in two rounds of byte permutes (v_perm_b32 picks bytes of
+// the pair {src0 : src1}, src1 holding bytes 0-3).
 template <int L>
 __device__ __forceinline__ void transpose_store(uint8_t* base, uint32_t plane, uint32_t off, const uint32_t (&w)[4]) {
-#pragma unroll
-  for (int i = 0; i < L; ++i) {
-    uint32_t v = ((w[0] >> (8 * i)) & 0xFF) | (((w[1] >> (8 * i)) & 0xFF) << 8) |
-                 (((w[2] >> (8 * i)) & 0xFF) << 16) | (((w[3] >> (8 * i)) & 0xFF) << 24);
-    *(uint32_t*)(base + i * plane + off) = v;
+  const uint32_t lo01 = __builtin_amdgcn_perm(w[1], w[0], 0x05010400u);  // w0.0 w1.0 w0.1 w1.1
+  const uint32_t lo23 = __builtin_amdgcn_perm(w[3], w[2], 0x05010400u);  // w2.0 w3.0 w2.1 w3.1
+  *(uint32_t*)(base + off) = __builtin_amdgcn_perm(lo23, lo01, 0x05040100u);
+  if constexpr (L > 1) *(uint32_t*)(base + plane + off) = __builtin_amdgcn_perm(lo23, lo01, 0x07060302u);
+  if constexpr (L > 2) {
+    const uint32_t hi01 = __builtin_amdgcn_perm(w[1], w[0], 0x07030602u);  // w0.2 w1.2 w0.3 w1.3
+    const uint32_t hi23 = __builtin_amdgcn_perm(w[3], w[2], 0x07030602u);
+    *(uint32_t*)(base + 2 * plane + off) = __builtin_amdgcn_perm(hi23, hi01, 0x05040100u);
+    if constexpr (L > 3) *(uint32_t*)(base + 3 * plane + off) = __builtin_amdgcn_perm(hi23, hi01, 0x07060302u);
   }
 }
 
@@ -423,6 +429,20 @@ __device__ __forceinline__ uint32_t slot_li(const GroupInfo& g, uint32_t s) {
   return s == 0 ? g.li[0] : s == 1 ? g.li[1] : s == 2 ? g.li[2] : g.li[3];
 }
 
+__device__ __forceinline__ uint32_t wave_uniform(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ uint64_t wave_uniform(uint64_t x) {
+  return ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(x >> 32)) << 32) |
+         __builtin_amdgcn_readfirstlane((uint32_t)x);
+}
+__device__ __forceinline__ uint64_t sel4(const uint64_t (&v)[4], uint32_t s) {
+  return s == 0 ? v[0] : s == 1 ? v[1] : s == 2 ? v[2] : v[3];
+}
+__device__ __forceinline__ uint32_t sel4(const uint32_t (&v)[4], uint32_t s) {
+  return s == 0 ? v[0] : s == 1 ? v[1] : s == 2 ? v[2] : v[3];
+}
+
+// The group's products and moduli; grp is the same in every lane, and so is the
+// result (kept in scalar registers).
 __device__ __forceinline__ GroupInfo group_info(const Mfma32Params& P, uint64_t grp) {
   GroupInfo gi;
   const uint32_t U = 1u << P.log2U;
@@ -437,6 +457,8 @@ __device__ __forceinline__ GroupInfo group_info(const Mfma32Params& P, uint64_t 
     gi.gp[s] = 0;
     gi.li[s] = 0;
     if ((uint32_t)s < gi.nslots) gi.gp[s] = global_product(P, gi.first + s, &gi.li[s]);
+    gi.gp[s] = wave_uniform(gi.gp[s]);
+    gi.li[s] = wave_uniform(gi.li[s]);
   }
   return gi;
 }
@@ -459,18 +481,15 @@ __device__ __forceinline__ void stage_a_item(const Mfma32Params& P, uint8_t* aba
                                              const ModQ32& m) {
   const uint32_t q = m.q, thr = m.thr, quarter = P.n >> 2;
   const uint32_t xr[4] = {reduce_u32(x.w, m), reduce_u32(x.z, m), reduce_u32(x.y, m), reduce_u32(x.x, m)};
-  uint32_t w[4];
+  uint32_t w[4], nw[4];
+  digits_pm32<L>(xr, q, thr, w, nw);
 #pragma unroll
-  for (int k = 0; k < 4; ++k) w[k] = digits32<L>(xr[k], q, thr);
+  for (int k = 0; k < 4; ++k)
+    if (P.cyclic) nw[k] = w[k];
   const uint32_t dw = ((P.E + 1) >> 2) - 1 - j;
   transpose_store<L>(abase, P.a_plane, dw * 4, w);
   const uint32_t dwn = dw + quarter;
-  if (dwn < (P.a_plane >> 2)) {
-    uint32_t nw[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) nw[k] = P.cyclic ? w[k] : neg_digits32<L>(xr[k], q, thr);
-    transpose_store<L>(abase, P.a_plane, dwn * 4, nw);
-  }
+  if (dwn < (P.a_plane >> 2)) transpose_store<L>(abase, P.a_plane, dwn * 4, nw);
 }
 
 // Word group e of b (row vs = e / (t/4), words 4wd..) into the staged B rows at
@@ -482,11 +501,10 @@ __device__ __forceinline__ void stage_b_item(const Mfma32Params& P, uint8_t* bba
   const uint32_t xr[4] = {reduce_u32(x.x, m), reduce_u32(x.y, m), reduce_u32(x.z, m), reduce_u32(x.w, m)};
   const int vs = (int)(e >> (P.log2t - 2)), wd = (int)(e & ((P.t >> 2) - 1));
   uint32_t w[4], nw[4];
+  digits_pm32<L>(xr, q, thr, w, nw);
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    w[k] = digits32<L>(xr[k], q, thr);
-    nw[k] = P.cyclic ? w[k] : neg_digits32<L>(xr[k], q, thr);
-  }
+  for (int k = 0; k < 4; ++k)
+    if (P.cyclic) nw[k] = w[k];
   const int rp = vs - v_lo, rn = vs - (int)P.r - v_lo;
   if (rp >= 0 && rp < (int)P.b_rows) transpose_store<L>(bbase, P.b_plane, rp * P.b_rowstride + wd * 4, w);
   if (rn >= 0 && rn < (int)P.b_rows) transpose_store<L>(bbase, P.b_plane, rn * P.b_rowstride + wd * 4, nw);
@@ -536,12 +554,35 @@ __device__ __forceinline__ void stage_zero_fill(const Mfma32Params& P, const Gro
 
 // Staging for n >= 1024: every run of 256 consecutive items lies in one slot and
 // is all A or all B (n/4 >= 256 items each), so slot, kind and modulus are
-// workgroup-uniform and each thread handles item (run, threadIdx.x).
+// workgroup-uniform and each thread handles item (run, threadIdx.x).  The slots'
+// operand offsets and modulus constants are looked up once, in scalar registers.
 template <int L>
 __device__ __forceinline__ void stage_uniform(const Mfma32Params& P, const GroupInfo& gi, uint8_t* smem) {
-  const uint32_t runs_per_slot = P.n >> 9, a_runs = P.n >> 10;  // (n/2) / 256 and (n/4) / 256
-  const uint32_t nruns = gi.nslots * runs_per_slot;
+  const uint32_t log2rps = P.log2n - 9, a_runs = P.n >> 10;  // runs per slot (n/2) / 256, of them a's (n/4) / 256
+  const uint32_t nruns = gi.nslots << log2rps, rmask = (1u << log2rps) - 1;
   const uint32_t tid = threadIdx.x;
+  // lane s < 4 of every wave holds slot s's word offsets and modulus constants; a
+  // run's slot (wave-uniform) then picks them with v_readlane, no branches
+  uint32_t lao, lao_hi, lbo, lbo_hi, lq, lthr, lm32;
+  {
+    uint64_t ao[4], bo[4];
+    uint32_t mq[4], mthr[4], mm32[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      ao[s] = gi.gp[s] * P.n;
+      bo[s] = b_product(P, gi.gp[s], gi.li[s]) * P.n;
+      const ModQ32& m = P.mods[gi.li[s]];
+      mq[s] = m.q;
+      mthr[s] = m.thr;
+      mm32[s] = m.m32;
+    }
+    const uint32_t ls = tid & 3;
+    const uint64_t a64 = sel4(ao, ls), b64 = sel4(bo, ls);
+    lao = (uint32_t)a64; lao_hi = (uint32_t)(a64 >> 32);
+    lbo = (uint32_t)b64; lbo_hi = (uint32_t)(b64 >> 32);
+    lq = sel4(mq, ls); lthr = sel4(mthr, ls); lm32 = sel4(mm32, ls);
+  }
+  auto pick = [](uint32_t v, uint32_t s) { return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)s); };
   for (uint32_t r0 = 0; r0 < nruns; r0 += kPrefetch) {
     uint4 pf[kPrefetch];
 #pragma unroll
@@ -549,18 +590,22 @@ __device__ __forceinline__ void stage_uniform(const Mfma32Params& P, const Group
       const uint32_t run = r0 + k;
       pf[k] = make_uint4(0, 0, 0, 0);
       if (run < nruns) {
-        const uint32_t sl = run / runs_per_slot, cr = run - sl * runs_per_slot;
-        const uint64_t gp = slot_gp(gi, sl);
-        if (cr < a_runs) pf[k] = ((const uint4*)(P.a + gp * P.n))[cr * 256 + tid];
-        else pf[k] = ((const uint4*)(P.b + b_product(P, gp, slot_li(gi, sl)) * P.n))[(cr - a_runs) * 256 + tid];
+        const uint32_t sl = run >> log2rps, cr = run & rmask;
+        const uint32_t* src =
+            cr < a_runs ? P.a + (((uint64_t)pick(lao_hi, sl) << 32) | pick(lao, sl)) + cr * 1024u
+                        : P.b + (((uint64_t)pick(lbo_hi, sl) << 32) | pick(lbo, sl)) + (cr - a_runs) * 1024u;
+        pf[k] = ((const uint4*)src)[tid];
       }
     }
 #pragma unroll
     for (int k = 0; k < kPrefetch; ++k) {
       const uint32_t run = r0 + k;
       if (run < nruns) {
-        const uint32_t sl = run / runs_per_slot, cr = run - sl * runs_per_slot;
-        const ModQ32& m = P.mods[slot_li(gi, sl)];
+        const uint32_t sl = run >> log2rps, cr = run & rmask;
+        ModQ32 m{};
+        m.q = pick(lq, sl);
+        m.thr = pick(lthr, sl);
+        m.m32 = pick(lm32, sl);
         uint8_t* slot = smem + sl * P.slot_bytes;
         if (cr < a_runs) stage_a_item<L>(P, slot, cr * 256 + tid, pf[k], m);
         else stage_b_item<L>(P, slot + L * P.a_plane, gi.v_lo, (cr - a_runs) * 256 + tid, pf[k], m);
