@@ -585,17 +585,16 @@ __device__ __forceinline__ void stage_uniform(const Mfma32Params& P, const Group
   auto pick = [](uint32_t v, uint32_t s) { return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)s); };
   for (uint32_t r0 = 0; r0 < nruns; r0 += kPrefetch) {
     uint4 pf[kPrefetch];
+    // every load is issued (a run past the end re-reads the last one), so the
+    // conversion below can start on run 0 while the later runs are in flight
 #pragma unroll
     for (int k = 0; k < kPrefetch; ++k) {
-      const uint32_t run = r0 + k;
-      pf[k] = make_uint4(0, 0, 0, 0);
-      if (run < nruns) {
-        const uint32_t sl = run >> log2rps, cr = run & rmask;
-        const uint32_t* src =
-            cr < a_runs ? P.a + (((uint64_t)pick(lao_hi, sl) << 32) | pick(lao, sl)) + cr * 1024u
-                        : P.b + (((uint64_t)pick(lbo_hi, sl) << 32) | pick(lbo, sl)) + (cr - a_runs) * 1024u;
-        pf[k] = ((const uint4*)src)[tid];
-      }
+      const uint32_t run = min(r0 + k, nruns - 1);
+      const uint32_t sl = run >> log2rps, cr = run & rmask;
+      const uint32_t* src =
+          cr < a_runs ? P.a + (((uint64_t)pick(lao_hi, sl) << 32) | pick(lao, sl)) + cr * 1024u
+                      : P.b + (((uint64_t)pick(lbo_hi, sl) << 32) | pick(lbo, sl)) + (cr - a_runs) * 1024u;
+      pf[k] = ((const uint4*)src)[tid];
     }
 #pragma unroll
     for (int k = 0; k < kPrefetch; ++k) {
