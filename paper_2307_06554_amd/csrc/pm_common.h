@@ -67,14 +67,21 @@ inline ModQ32 make_mod32(uint32_t q, int L) {
   return m;
 }
 
-// Barrett: x mod q for any 64-bit x, q < 2^32.  With mu = floor(2^64/q) the
-// quotient estimate undershoots by at most 2, so r < 3q < 2^34.
+// Barrett: x mod q for any 64-bit x, q < 2^32.  With mu = floor(2^64/q) >=
+// 2^64/q - 1 and x < 2^64, x*mu/2^64 > x/q - 1, so the quotient estimate is
+// floor(x/q) or one less and r = x - estimate*q lies in [0, 2q).
 __device__ __forceinline__ uint32_t reduce_u64(uint64_t x, const ModQ32& m) {
-  uint64_t qe = __umul64hi(x, m.mu);
+  const uint64_t qe = __umul64hi(x, m.mu);
   uint64_t r = x - qe * (uint64_t)m.q;
   if (r >= m.q) r -= m.q;
-  if (r >= m.q) r -= m.q;
   return (uint32_t)r;
+}
+// The same for q < 2^31: then r < 2q < 2^32, so r is the low word of
+// x - estimate*q and the tail is 32-bit arithmetic.
+__device__ __forceinline__ uint32_t reduce_u64_q31(uint64_t x, uint64_t mu, uint32_t q) {
+  const uint64_t qe = __umul64hi(x, mu);
+  const uint32_t r = (uint32_t)x - (uint32_t)qe * q;
+  return min(r, r - q);
 }
 // x mod q for a 32-bit word.  With m32 = floor(2^32/q) >= 2^32/q - 1 and x < 2^32,
 // x*m32/2^32 > x/q - 1, so the estimate floor(x*m32/2^32) is floor(x/q) or one
@@ -86,9 +93,9 @@ __device__ __forceinline__ uint32_t reduce_u32(uint32_t x, const ModQ32& m) {
   const uint32_t r = x - qe * m.q;
   return min(r, r - m.q);
 }
-// Signed |x| < 2^62.
+// Signed |x| < 2^62 (x + lift is in (0, 2^63 + 2^32), added as unsigned words).
 __device__ __forceinline__ uint32_t reduce_i64(int64_t x, const ModQ32& m) {
-  return reduce_u64((uint64_t)(x + (int64_t)m.lift), m);
+  return reduce_u64((uint64_t)x + m.lift, m);
 }
 
 // L digits of the residue x (already in [0, q)), packed little-endian in a word.

@@ -334,18 +334,37 @@ __device__ __forceinline__ void mfma32_tile(const Mfma32Params& P, const uint8_t
 // Recombination c = sum_s T_s 2^(8s) mod q of the 16 outputs a lane holds, then
 // the stores.
 template <int L>
-__device__ __forceinline__ void mfma32_reduce(const Mfma32Params& P, const ModQ32& m, const int32_t* rc,
+__device__ __forceinline__ void mfma32_reduce(const Mfma32Params& P, const ModQ32& mp, const int32_t* rcp,
                                               const v16i (&acc)[2 * L - 1], uint32_t (&out)[16]) {
+  // constants read once (the loops below would otherwise reload them per value)
+  const ModQ32 m = mp;
+  int32_t rc[2 * L - 1];
 #pragma unroll
-  for (int rr = 0; rr < 16; ++rr) {
-    if (P.fast_epilogue) {
-      // sum_s T_s * (2^(8s) mod q, centred) stays below 2^62 in magnitude (checked on the host).
-      int64_t x = 0;
+  for (int s = 0; s < 2 * L - 1; ++s) rc[s] = rcp[s];
+  if (P.fast_epilogue) {
+    // sum_s T_s * (2^(8s) mod q, centred) stays below 2^62 in magnitude (checked on
+    // the host); adding lift makes it non-negative
+    if (m.q < 0x80000000u) {
 #pragma unroll
-      for (int s = 0; s < 2 * L - 1; ++s) x += (int64_t)acc[s][rr] * (int64_t)rc[s];
-      out[rr] = reduce_i64(x, m);
+      for (int rr = 0; rr < 16; ++rr) {
+        uint64_t x = m.lift;  // unsigned words: the sum may pass 2^63
+#pragma unroll
+        for (int s = 0; s < 2 * L - 1; ++s) x += (uint64_t)((int64_t)acc[s][rr] * (int64_t)rc[s]);
+        out[rr] = reduce_u64_q31(x, m.mu, m.q);
+      }
     } else {
-      // Horner in radix 2^8 from the top shift class down.
+#pragma unroll
+      for (int rr = 0; rr < 16; ++rr) {
+        int64_t x = 0;
+#pragma unroll
+        for (int s = 0; s < 2 * L - 1; ++s) x += (int64_t)acc[s][rr] * (int64_t)rc[s];
+        out[rr] = reduce_i64(x, m);
+      }
+    }
+  } else {
+    // Horner in radix 2^8 from the top shift class down.
+#pragma unroll
+    for (int rr = 0; rr < 16; ++rr) {
       uint32_t v = reduce_i64((int64_t)acc[2 * L - 2][rr], m);
 #pragma unroll
       for (int s = 2 * L - 3; s >= 0; --s) v = reduce_i64((int64_t)v * 256 + (int64_t)acc[s][rr], m);
