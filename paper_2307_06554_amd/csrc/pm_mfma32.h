@@ -571,17 +571,17 @@ __device__ __forceinline__ void stage_zero_fill(const Mfma32Params& P, const Gro
   for (uint32_t s = 0; s < gi.nslots; ++s) zero_fill_b<L>(P, smem + s * P.slot_bytes + L * P.a_plane, gi.v_lo);
 }
 
-// Staging for n >= 1024: every run of 256 consecutive items lies in one slot and
-// is all A or all B (n/4 >= 256 items each), so slot, kind and modulus are
-// workgroup-uniform and each thread handles item (run, threadIdx.x).  The slots'
-// operand offsets and modulus constants are looked up once, in scalar registers.
+// Staging for n >= 256.  The group's items, in order (slot, then a's n/4 word
+// groups, then b's), fall into runs of 64 that each lie in one slot and one
+// operand (n/4 >= 64), so wave w takes runs w, w + 4, ... and slot, operand and
+// modulus are uniform over the wave; lane l handles item 64 run + l.  The slots'
+// operand offsets and modulus constants sit in lanes 0..3 and are picked with
+// v_readlane, so the per-run selection has no branches.
 template <int L>
-__device__ __forceinline__ void stage_uniform(const Mfma32Params& P, const GroupInfo& gi, uint8_t* smem) {
-  const uint32_t log2rps = P.log2n - 9, a_runs = P.n >> 10;  // runs per slot (n/2) / 256, of them a's (n/4) / 256
+__device__ __forceinline__ void stage_runs(const Mfma32Params& P, const GroupInfo& gi, uint8_t* smem) {
+  const uint32_t log2rps = P.log2n - 7, a_runs = P.n >> 8;  // runs per slot (n/2) / 64, of them a's (n/4) / 64
   const uint32_t nruns = gi.nslots << log2rps, rmask = (1u << log2rps) - 1;
-  const uint32_t tid = threadIdx.x;
-  // lane s < 4 of every wave holds slot s's word offsets and modulus constants; a
-  // run's slot (wave-uniform) then picks them with v_readlane, no branches
+  const uint32_t lane = threadIdx.x & 63, wave = wave_uniform(threadIdx.x >> 6);
   uint32_t lao, lao_hi, lbo, lbo_hi, lq, lthr, lm32;
   {
     uint64_t ao[4], bo[4];
@@ -595,29 +595,31 @@ __device__ __forceinline__ void stage_uniform(const Mfma32Params& P, const Group
       mthr[s] = m.thr;
       mm32[s] = m.m32;
     }
-    const uint32_t ls = tid & 3;
+    const uint32_t ls = lane & 3;
     const uint64_t a64 = sel4(ao, ls), b64 = sel4(bo, ls);
     lao = (uint32_t)a64; lao_hi = (uint32_t)(a64 >> 32);
     lbo = (uint32_t)b64; lbo_hi = (uint32_t)(b64 >> 32);
     lq = sel4(mq, ls); lthr = sel4(mthr, ls); lm32 = sel4(mm32, ls);
   }
   auto pick = [](uint32_t v, uint32_t s) { return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)s); };
-  for (uint32_t r0 = 0; r0 < nruns; r0 += kPrefetch) {
+  if (wave >= nruns) return;
+  const uint32_t last = wave + 4 * ((nruns - 1 - wave) >> 2);  // this wave's last run
+  for (uint32_t r0 = wave; r0 < nruns; r0 += 4 * kPrefetch) {
+    // every load is issued (a run past this wave's last re-reads the last one),
+    // so the conversion below can start on the first run while the rest are in flight
     uint4 pf[kPrefetch];
-    // every load is issued (a run past the end re-reads the last one), so the
-    // conversion below can start on run 0 while the later runs are in flight
 #pragma unroll
     for (int k = 0; k < kPrefetch; ++k) {
-      const uint32_t run = min(r0 + k, nruns - 1);
+      const uint32_t run = min(r0 + 4 * k, last);
       const uint32_t sl = run >> log2rps, cr = run & rmask;
       const uint32_t* src =
-          cr < a_runs ? P.a + (((uint64_t)pick(lao_hi, sl) << 32) | pick(lao, sl)) + cr * 1024u
-                      : P.b + (((uint64_t)pick(lbo_hi, sl) << 32) | pick(lbo, sl)) + (cr - a_runs) * 1024u;
-      pf[k] = ((const uint4*)src)[tid];
+          cr < a_runs ? P.a + (((uint64_t)pick(lao_hi, sl) << 32) | pick(lao, sl)) + cr * 256u
+                      : P.b + (((uint64_t)pick(lbo_hi, sl) << 32) | pick(lbo, sl)) + (cr - a_runs) * 256u;
+      pf[k] = ((const uint4*)src)[lane];
     }
 #pragma unroll
     for (int k = 0; k < kPrefetch; ++k) {
-      const uint32_t run = r0 + k;
+      const uint32_t run = r0 + 4 * k;
       if (run < nruns) {
         const uint32_t sl = run >> log2rps, cr = run & rmask;
         ModQ32 m{};
@@ -625,8 +627,8 @@ __device__ __forceinline__ void stage_uniform(const Mfma32Params& P, const Group
         m.thr = pick(lthr, sl);
         m.m32 = pick(lm32, sl);
         uint8_t* slot = smem + sl * P.slot_bytes;
-        if (cr < a_runs) stage_a_item<L>(P, slot, cr * 256 + tid, pf[k], m);
-        else stage_b_item<L>(P, slot + L * P.a_plane, gi.v_lo, (cr - a_runs) * 256 + tid, pf[k], m);
+        if (cr < a_runs) stage_a_item<L>(P, slot, cr * 64 + lane, pf[k], m);
+        else stage_b_item<L>(P, slot + L * P.a_plane, gi.v_lo, (cr - a_runs) * 64 + lane, pf[k], m);
       }
     }
   }
@@ -644,8 +646,8 @@ __device__ __forceinline__ void resident_group(const Mfma32Params& P, uint64_t g
     for (uint32_t s = 0; s < gi.nslots; ++s)
       mfma32_stage<L>(P, smem + s * P.slot_bytes, slot_gp(gi, s), b_product(P, slot_gp(gi, s), slot_li(gi, s)),
                       P.mods[slot_li(gi, s)], gi.v_lo);
-  } else if (P.n >= 1024) {
-    stage_uniform<L>(P, gi, smem);
+  } else if (P.n >= 256) {
+    stage_runs<L>(P, gi, smem);
     stage_zero_fill<L>(P, gi, smem);
   } else {
     // all loads of a pass are issued before any is converted
@@ -690,7 +692,7 @@ __device__ __forceinline__ void resident_group_split(const Mfma32Params& P, uint
   const uint32_t grp = item / P.kparts, part = item - grp * P.kparts;
   const uint32_t U = 1u << P.log2U;
   const GroupInfo gi = group_info(P, grp);
-  stage_uniform<L>(P, gi, smem);  // split groups have n >= 2048
+  stage_runs<L>(P, gi, smem);  // split groups have n >= 2048
   stage_zero_fill<L>(P, gi, smem);
   __syncthreads();
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
