@@ -231,25 +231,28 @@ __device__ __forceinline__ void item_write(const StreamParams& P, const StreamIt
   }
 }
 
-// Running residues: res = (res + sum_s T_s 2^(8s)) mod q, then T_s = 0.
-// sum_s T_s (2^(8s) mod q) is formed exactly as a signed 128-bit value
-// (|T_s| < 2^31, 2L-1 <= 15 terms of < 2^95 each) and reduced once.
+// Running residues: res = (res + sum_s T_s 2^(8s)) mod q, then T_s = 0.  The
+// classes are taken four at a time: Y_j = sum_{k<4} T_{4j+k} 2^(8k) is exact in
+// int64 (|Y_j| < 2^31 (1 + 2^8 + 2^16 + 2^24) < 2^56), and with R_j = 2^(32j) mod q
+// the sum sum_j (Y_j + 2^56) R_j is a non-negative integer below 4 * 2^57 * 2^64
+// = 2^123.  One remainder of it, less foff = (2^56 sum_j R_j) mod q, is the
+// flush's contribution (sum_s T_s 2^(8s) = sum_j Y_j 2^(32j)).
 template <int L, typename W>
 __device__ __forceinline__ void stream_flush(v16i (&acc)[2 * L - 1], W (&res)[16], const ModQ64& m) {
+  constexpr int S = 2 * L - 1, G = (S + 3) / 4;
 #pragma unroll
   for (int rr = 0; rr < 16; ++rr) {
     U128 x{0, 0};
 #pragma unroll
-    for (int s = 0; s < 2 * L - 1; ++s) {
-      const int32_t tv = acc[s][rr];
-      const U128 p = mul64x64((uint64_t)(tv < 0 ? -(int64_t)tv : (int64_t)tv), m.r[s]);
-      if (tv >= 0) x = add128(x, p);
-      else x = add128(x, U128{~p.lo + 1, ~p.hi + (p.lo == 0 ? 1u : 0u)});  // two's complement
+    for (int j = 0; j < G; ++j) {
+      int64_t y = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (4 * j + k < S) y += (int64_t)acc[4 * j + k][rr] * ((int64_t)1 << (8 * k));
+      const uint64_t yo = (uint64_t)y + ((uint64_t)1 << 56);  // in (0, 2^57)
+      x = add128(x, j == 0 ? U128{yo, 0} : mul64x64(yo, m.r[4 * j]));
     }
-    const bool negative = (int64_t)x.hi < 0;
-    if (negative) x = U128{~x.lo + 1, ~x.hi + (x.lo == 0 ? 1u : 0u)};
-    uint64_t v = mod_u128(x.hi, x.lo, m);
-    if (negative && v) v = m.q - v;
+    const uint64_t v = submod64(mod_u128(x.hi, x.lo, m), m.foff, m.q);
     res[rr] = (W)addmod64((uint64_t)res[rr], v, m.q);
     __builtin_amdgcn_sched_barrier(0);
   }

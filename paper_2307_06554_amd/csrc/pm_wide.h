@@ -54,6 +54,7 @@ struct ModQ64 {
   uint32_t sh;      // normalisation shift, 0..63
   uint32_t pad;
   uint64_t r[16];   // 2^(8s) mod q for s < 15
+  uint64_t foff;    // (2^56 * sum_j 2^(32j)) mod q over the ceil((2L-1)/4) class groups of a flush
 };
 
 // One 2/1 division step: (u1, u0) with u1 < d -> remainder mod d.

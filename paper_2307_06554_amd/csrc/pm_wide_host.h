@@ -19,6 +19,10 @@ inline ModQ64 make_mod64(uint64_t q, int L) {
     m.r[s] = (uint64_t)pw;
     pw = (pw * 256) % q;
   }
+  const int groups = (2 * L - 1 + 3) / 4;
+  unsigned __int128 rsum = 0;
+  for (int j = 0; j < groups; ++j) rsum = (rsum + m.r[4 * j]) % q;
+  m.foff = (uint64_t)((((unsigned __int128)1 << 56) % q) * rsum % q);
   return m;
 }
 
