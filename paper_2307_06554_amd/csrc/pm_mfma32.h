@@ -254,6 +254,41 @@ __device__ __forceinline__ void mfma_step(v16i (&acc)[2 * L - 1], const v4i (&a)
   }
 }
 
+// The same K-step with the next step's A fragments aligned in place during the
+// last column: right after the column's MFMA on limb i (the last to read a[i]),
+// a[i] takes limb i of the next step (its runs read a step earlier) and the raw
+// registers are re-read for the step after that, so no bubble separates the
+// steps and no second A register set is needed.
+template <int L>
+__device__ __forceinline__ void mfma_step_tail(v16i (&acc)[2 * L - 1], v4i (&a)[L], uint32_t (&araw)[L][5],
+                                               uint32_t sh_next, const uint8_t* aplane, uint32_t a_plane,
+                                               int S_after, v4i (&b)[L], const uint8_t* bplane, uint32_t b_plane,
+                                               int boff_next) {
+#pragma unroll
+  for (int j = 0; j < L - 1; ++j) {
+#pragma unroll
+    for (int i = 0; i < L; ++i)
+      acc[i + j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], b[j], acc[i + j], 0, 0, 0);
+    b[j] = *(const v4i*)(bplane + j * b_plane + boff_next);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  constexpr int j = L - 1;
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    acc[i + j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], b[j], acc[i + j], 0, 0, 0);
+    a[i][0] = (int)__builtin_amdgcn_alignbyte(araw[i][1], araw[i][0], sh_next);
+    a[i][1] = (int)__builtin_amdgcn_alignbyte(araw[i][2], araw[i][1], sh_next);
+    a[i][2] = (int)__builtin_amdgcn_alignbyte(araw[i][3], araw[i][2], sh_next);
+    a[i][3] = (int)__builtin_amdgcn_alignbyte(araw[i][4], araw[i][3], sh_next);
+    const uint32_t* p = (const uint32_t*)(aplane + i * a_plane) + (S_after >> 2);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) araw[i][k] = p[k];
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  b[j] = *(const v4i*)(bplane + j * b_plane + boff_next);
+  __builtin_amdgcn_sched_barrier(0);
+}
+
 // The same K-step with the A fragments double-buffered: with column j, limb j
 // of the next step's runs (read one step earlier) is aligned into `an` and the
 // limb's runs of the step after that are read, so the next step starts

@@ -345,15 +345,16 @@ __device__ __forceinline__ void stream_block(const StreamParams& P, uint64_t ite
         const int d = D0 + (st >> P.log2spd);
         return ((u0 + zl - d) & (kRing - 1)) * rs + ((st & ((int)P.spd - 1)) << 5) + 16 * g;
       };
-      int S = S_of(0);
-      araw_load<L>(araw, abuf, P.a_win, S);
+      // af: step st aligned; araw: step st + 1's runs; the last steps re-read their own
+      araw_load<L>(araw, abuf, P.a_win, S_of(0));
+      a_align<L>(af, araw, (uint32_t)(S_of(0) & 3));
+      araw_load<L>(araw, abuf, P.a_win, S_of(steps > 1 ? 1 : 0));
       b_load<L>(b, ring, kRing * P.rs, B_of(0));
       for (int st = 0; st < steps; ++st) {
-        a_align<L>(af, araw, (uint32_t)(S & 3));
-        const int sn = st + 1 < steps ? st + 1 : st;  // the last step re-reads its own runs
-        S = S_of(sn);
-        araw_load<L>(araw, abuf, P.a_win, S);
-        mfma_step<L>(acc, af, b, ring, kRing * P.rs, B_of(sn));
+        const int sn = st + 1 < steps ? st + 1 : st;
+        const int s2 = st + 2 < steps ? st + 2 : steps - 1;
+        mfma_step_tail<L>(acc, af, araw, (uint32_t)(S_of(sn) & 3), abuf, P.a_win, S_of(s2), b, ring,
+                          kRing * P.rs, B_of(sn));
       }
       if (!more || (c + 1 - c0) % (int)P.flush_every == 0) stream_flush<L, W>(acc, res, m);
     }
