@@ -43,6 +43,7 @@ struct StreamParams {
   uint32_t flush_every;   // chunks between int32 -> residue flushes
   uint32_t a_win;         // bytes per limb of one A window buffer
   uint32_t lds_b;         // LDS offset of the B ring
+  uint32_t lds_res;       // L = 8: LDS offset of the running residues, [16][256] words
   uint32_t lc, nq_total, l0;  // product i -> global (i/lc)*nq_total + l0 + i%lc, modulus i%lc
   uint32_t lrep;              // > 1: product i is global i with modulus (i/lrep)%lc
   uint32_t b_shared;          // 1: one b per channel, b + (l0 + channel) * n, for every product
@@ -237,23 +238,33 @@ __device__ __forceinline__ void item_write(const StreamParams& P, const StreamIt
 // the sum sum_j (Y_j + 2^56) R_j is a non-negative integer below 4 * 2^57 * 2^64
 // = 2^123.  One remainder of it, less foff = (2^56 sum_j R_j) mod q, is the
 // flush's contribution (sum_s T_s 2^(8s) = sum_j Y_j 2^(32j)).
-template <int L, typename W>
-__device__ __forceinline__ void stream_flush(v16i (&acc)[2 * L - 1], W (&res)[16], const ModQ64& m) {
+template <int L>
+__device__ __forceinline__ uint64_t flush_value(const v16i (&acc)[2 * L - 1], int rr, const ModQ64& m) {
   constexpr int S = 2 * L - 1, G = (S + 3) / 4;
+  U128 x{0, 0};
+#pragma unroll
+  for (int j = 0; j < G; ++j) {
+    int64_t y = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (4 * j + k < S) y += (int64_t)acc[4 * j + k][rr] * ((int64_t)1 << (8 * k));
+    const uint64_t yo = (uint64_t)y + ((uint64_t)1 << 56);  // in (0, 2^57)
+    x = add128(x, j == 0 ? U128{yo, 0} : mul64x64(yo, m.r[4 * j]));
+  }
+  return submod64(mod_u128(x.hi, x.lo, m), m.foff, m.q);
+}
+// Residues in registers (res) or, for L = 8, in LDS (resl: word rr of thread i at rr * 256 + i).
+template <int L, typename W, int N>
+__device__ __forceinline__ void stream_flush(v16i (&acc)[2 * L - 1], W (&res)[N], W* resl, const ModQ64& m) {
 #pragma unroll
   for (int rr = 0; rr < 16; ++rr) {
-    U128 x{0, 0};
-#pragma unroll
-    for (int j = 0; j < G; ++j) {
-      int64_t y = 0;
-#pragma unroll
-      for (int k = 0; k < 4; ++k)
-        if (4 * j + k < S) y += (int64_t)acc[4 * j + k][rr] * ((int64_t)1 << (8 * k));
-      const uint64_t yo = (uint64_t)y + ((uint64_t)1 << 56);  // in (0, 2^57)
-      x = add128(x, j == 0 ? U128{yo, 0} : mul64x64(yo, m.r[4 * j]));
+    const uint64_t v = flush_value<L>(acc, rr, m);
+    if constexpr (L == 8) {
+      W& r = resl[rr * kStreamThreads + threadIdx.x];
+      r = (W)addmod64((uint64_t)r, v, m.q);
+    } else {
+      res[rr] = (W)addmod64((uint64_t)res[rr], v, m.q);
     }
-    const uint64_t v = submod64(mod_u128(x.hi, x.lo, m), m.foff, m.q);
-    res[rr] = (W)addmod64((uint64_t)res[rr], v, m.q);
     __builtin_amdgcn_sched_barrier(0);
   }
 #pragma unroll
@@ -302,9 +313,14 @@ __device__ __forceinline__ void stream_block(const StreamParams& P, uint64_t ite
   v16i acc[2 * L - 1];
 #pragma unroll
   for (int s = 0; s < 2 * L - 1; ++s) acc[s] = v16i{};
-  W res[16];
+  // running residues: registers, or LDS for L = 8 (one wave per SIMD and every register taken)
+  W res[L == 8 ? 1 : 16];
+  W* resl = (W*)(smem + P.lds_res);
 #pragma unroll
-  for (int rr = 0; rr < 16; ++rr) res[rr] = 0;
+  for (int rr = 0; rr < 16; ++rr) {
+    if constexpr (L == 8) resl[rr * kStreamThreads + threadIdx.x] = 0;
+    else res[rr] = 0;
+  }
 
   // per-lane A base: S = S_base + (dc - 1 - dl) t + w0 inside the chunk's window
   const int S_base = 32 * (int)P.tz - 1 - z0 - zl + 16 * g;
@@ -356,7 +372,7 @@ __device__ __forceinline__ void stream_block(const StreamParams& P, uint64_t ite
         mfma_step_tail<L>(acc, af, araw, (uint32_t)(S_of(sn) & 3), abuf, P.a_win, S_of(s2), b, ring,
                           kRing * P.rs, B_of(sn));
       }
-      if (!more || (c + 1 - c0) % (int)P.flush_every == 0) stream_flush<L, W>(acc, res, m);
+      if (!more || (c + 1 - c0) % (int)P.flush_every == 0) stream_flush<L, W>(acc, res, resl, m);
     }
     if (!more) break;
     // ---- convert and write the next chunk (its A buffer and ring rows are not read now)
@@ -379,16 +395,19 @@ __device__ __forceinline__ void stream_block(const StreamParams& P, uint64_t ite
     }
     __syncthreads();
   }
+  if (!active) return;
 
   // ---- store the residues: lane holds z = z0 + 8 blk + 4 g + e, u = u0 + zl
-  if (!active) return;
   const int u = u0 + zl;
   if (u >= (int)P.r) return;
   W* C = (P.kparts > 1 ? (W*)P.part_ws + (uint64_t)part * P.nprod * P.n : (W*)P.c) + gp * P.n;
 #pragma unroll
   for (int rr = 0; rr < 16; ++rr) {
     const int z = z0 + 8 * (rr >> 2) + 4 * g + (rr & 3);
-    if (z < t) C[(size_t)u * t + z] = res[rr];
+    if (z < t) {
+      if constexpr (L == 8) C[(size_t)u * t + z] = resl[rr * kStreamThreads + threadIdx.x];
+      else C[(size_t)u * t + z] = res[rr];
+    }
   }
 }
 

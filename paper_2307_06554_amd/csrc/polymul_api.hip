@@ -409,7 +409,8 @@ polymul_status fill_stream(StreamParams& P, const void* a, const void* b, void* 
   P.b_shared = b_shared ? 1u : 0u;
   P.kparts = 1;
   for (uint32_t i = 0; i < lc; ++i) P.mods[i] = make_mod64(qs[i], L);
-  *lds = P.lds_b + (uint32_t)L * kRing * P.rs;
+  P.lds_res = P.lds_b + (uint32_t)L * kRing * P.rs;
+  *lds = P.lds_res + (L == 8 ? 16u * kStreamThreads * 8u : 0u);
   return *lds <= kMaxLds ? POLYMUL_OK : POLYMUL_EUNSUPPORTED;
 }
 
