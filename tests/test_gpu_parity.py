@@ -55,6 +55,21 @@ def test_mfma_noncanonical_words(q):
     _check(pm.polymul_negacyclic, a, b, q)
 
 
+@pytest.mark.parametrize("q", [2, 3, 3329, Q30, (1 << 31) - 1, 1 << 31, (1 << 31) + 6, (1 << 32) - 5])
+def test_mfma_word_reduction_extremes(q):
+    """Input words at the top of the 32-bit range and next to multiples of q, where a
+    word's quotient estimate is furthest off, through every staging path (n < 256,
+    n >= 256) and both epilogue forms (q below and above 2^31)."""
+    k = ((1 << 32) - 1) // q
+    words = {(1 << 32) - 1, (1 << 32) - 2, (1 << 32) - q, k * q, k * q - 1, (k - 1) * q + q - 1, q, q - 1, 0}
+    words = np.array(sorted(w for w in words if 0 <= w < (1 << 32)), dtype=np.uint64)
+    rng = np.random.Generator(np.random.PCG64(q % 65521))
+    for n in (64, 256, 1024, 4096):
+        a = rng.choice(words, size=(3, n)).astype(np.uint32)
+        b = rng.choice(words, size=(3, n)).astype(np.uint32)
+        _check(pm.polymul_negacyclic, a, b, q)
+
+
 @pytest.mark.parametrize("q", [257, 65537, Q30, (1 << 32) - 5])
 def test_mfma_digit_window_edges(q):
     """Representatives at the edges of the balanced-digit window and words whose
