@@ -108,9 +108,10 @@ polymul_status polymul_negacyclic_plain(const uint32_t* a, const uint32_t* b, ui
  *   a, b, c: device, count*n words of elem_bytes (4: q < 2^32; 8: q < 2^64).
  * polymul_plan_create copies the group table, builds and uploads the work
  * list and captures the graph; the plan owns only that device work list, its
- * queue counter, the graph and, when it cuts large items along K into runs
- * (items that would take more than an even share of the work), the buffer
- * the runs leave their residues in.  Pointers are baked in: later executes read
+ * queue counters (left at zero by every launch), the graph and, when it cuts
+ * large items along K into runs (items that would take more than an even share
+ * of the work), the buffer the runs leave their residues in and the table of
+ * the sums that one more launch forms from them.  Pointers are baked in: later executes read
  * and write the same buffers.  A plan must not be executed concurrently with
  * itself.  flags: 0, or POLYMUL_PLAN_NO_GRAPH to launch directly each time.
  */

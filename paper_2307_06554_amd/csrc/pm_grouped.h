@@ -27,11 +27,10 @@ struct WorkItem {
   uint32_t index;    // resident: tile-group index; stream: product * ublocks + u-block
 };
 
-// Resets the queue counter (a kernel, not a memset, so the graph holds no memset node).
-__global__ void reset_counter_kernel(uint32_t* counter) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) counter[0] = 0u;
-}
-
+// counter[0] is the queue, counter[1] counts the workgroups that have left; the last
+// to leave sets both back to zero, so that the next launch (a graph replay) starts
+// from an empty queue without a reset node.  Every workgroup's final claim has
+// returned before it counts itself out, so no claim can follow the reset.
 template <int L>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void grouped_kernel(const GroupJob* __restrict__ jobs, const WorkItem* __restrict__ items, uint32_t nitems,
@@ -43,7 +42,13 @@ void grouped_kernel(const GroupJob* __restrict__ jobs, const WorkItem* __restric
     __syncthreads();
     const uint32_t it = claimed;
     __syncthreads();  // every wave has read `claimed` before it is written again
-    if (it >= nitems) break;  // uniform: every wave leaves together
+    if (it >= nitems) {  // uniform: every wave leaves together
+      if (threadIdx.x == 0 && atomicAdd(counter + 1, 1u) == gridDim.x - 1) {
+        atomicExch(counter, 0u);
+        atomicExch(counter + 1, 0u);
+      }
+      break;
+    }
     const WorkItem w = items[it];
     const GroupJob& job = jobs[w.group];
     if (job.kind == kJobResident) {

@@ -748,17 +748,29 @@ __device__ __forceinline__ void resident_group_split(const Mfma32Params& P, uint
   mfma32_store(Q, gprod, 32 * zt, 32 * ut, out);
 }
 
-// c = sum of the kparts runs' residues mod q, word by word (one plan job).
-__global__ __launch_bounds__(256) void split_sum_kernel(const uint32_t* __restrict__ ws, uint32_t* __restrict__ c,
-                                                        uint64_t words, uint32_t kparts, ModQ32 m) {
-  const uint64_t i = ((uint64_t)blockIdx.x * 256 + threadIdx.x) * 4;
-  if (i >= words) return;  // words is a multiple of 4
+// c = sum of the kparts runs' residues mod q, word by word, for every K-split job of
+// a plan in one launch: segment k owns blocks [first_block, next first_block).
+struct SplitSeg {
+  const uint32_t* ws;  // [kparts][words]
+  uint32_t* c;
+  uint64_t words;      // a multiple of 4
+  uint32_t kparts;
+  uint32_t first_block;
+  ModQ32 m;
+};
+__global__ __launch_bounds__(256) void split_sum_kernel(const SplitSeg* __restrict__ segs, uint32_t nseg) {
+  uint32_t k = 0;
+  while (k + 1 < nseg && segs[k + 1].first_block <= blockIdx.x) ++k;  // uniform: a few segments
+  const SplitSeg& sg = segs[k];
+  const uint64_t i = ((uint64_t)(blockIdx.x - sg.first_block) * 256 + threadIdx.x) * 4;
+  if (i >= sg.words) return;
   uint64_t s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-  for (uint32_t p = 0; p < kparts; ++p) {
-    const uint4 x = *(const uint4*)(ws + (uint64_t)p * words + i);
+  for (uint32_t p = 0; p < sg.kparts; ++p) {
+    const uint4 x = *(const uint4*)(sg.ws + (uint64_t)p * sg.words + i);
     s0 += x.x; s1 += x.y; s2 += x.z; s3 += x.w;
   }
-  *(uint4*)(c + i) = make_uint4(reduce_u64(s0, m), reduce_u64(s1, m), reduce_u64(s2, m), reduce_u64(s3, m));
+  *(uint4*)(sg.c + i) =
+      make_uint4(reduce_u64(s0, sg.m), reduce_u64(s1, sg.m), reduce_u64(s2, sg.m), reduce_u64(s3, sg.m));
 }
 
 // One group of four 32x32 tiles per workgroup.

@@ -530,16 +530,11 @@ __global__ __launch_bounds__(256) void split_sum64_kernel(const uint64_t* __rest
 struct polymul_plan {
   GroupJob* d_jobs = nullptr;       // device job table
   WorkItem* d_items = nullptr;      // device work list (largest first)
-  uint32_t* d_counter = nullptr;    // queue counter
+  uint32_t* d_counter = nullptr;    // queue counter and workgroups-left counter (zero between launches)
   void* d_part_ws = nullptr;        // residues of K-split runs
-  struct SplitSum {                 // one K-split job: c = sum of its runs mod q
-    const uint32_t* ws;
-    uint32_t* c;
-    uint64_t words;
-    uint32_t kparts;
-    ModQ32 m;
-  };
-  std::vector<SplitSum> sums;
+  std::vector<SplitSeg> segs;       // K-split jobs: c = sum of their runs mod q, one launch for all
+  SplitSeg* d_segs = nullptr;
+  uint32_t sum_blocks = 0;
   uint32_t nitems = 0;
   uint32_t lds = 0;                 // dynamic LDS of the grouped launch
   uint32_t grid = 0;
@@ -564,15 +559,13 @@ polymul_status plan_attrs() {
 
 polymul_status plan_launch(const polymul_plan* p, hipStream_t s) {
   if (p->nitems) {
-    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, p->d_counter);
     hipLaunchKernelGGL(grouped_kernel<4>, dim3(p->grid), dim3(kThreads), p->lds, s, p->d_jobs, p->d_items,
                        p->nitems, p->d_counter);
     polymul_status st = launch_status();
     if (st != POLYMUL_OK) return st;
-    for (const auto& sum : p->sums) {
-      const uint64_t blocks = (sum.words / 4 + 255) / 256;
-      hipLaunchKernelGGL(split_sum_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, sum.ws, sum.c, sum.words,
-                         sum.kparts, sum.m);
+    if (!p->segs.empty()) {
+      hipLaunchKernelGGL(split_sum_kernel, dim3(p->sum_blocks), dim3(256), 0, s, p->d_segs,
+                         (uint32_t)p->segs.size());
       st = launch_status();
       if (st != POLYMUL_OK) return st;
     }
@@ -594,6 +587,7 @@ void plan_free(polymul_plan* p) {
   if (p->d_items) (void)hipFree(p->d_items);
   if (p->d_counter) (void)hipFree(p->d_counter);
   if (p->d_part_ws) (void)hipFree(p->d_part_ws);
+  if (p->d_segs) (void)hipFree(p->d_segs);
   delete p;
 }
 
@@ -801,17 +795,32 @@ polymul_status polymul_plan_create(polymul_plan** plan, const polymul_group* gro
       for (GroupJob& j : jobs) {
         if (j.kind == kJobStream && j.sp.kparts > 1) {
           j.sp.part_ws = (uint32_t*)p->d_part_ws + (uintptr_t)j.sp.part_ws;
-          p->sums.push_back({(const uint32_t*)j.sp.part_ws, (uint32_t*)j.sp.c, j.sp.nprod * j.sp.n, j.sp.kparts,
-                             make_mod32((uint32_t)j.sp.mods[0].q, 4)});
+          p->segs.push_back({(const uint32_t*)j.sp.part_ws, (uint32_t*)j.sp.c, j.sp.nprod * j.sp.n, j.sp.kparts,
+                             0, make_mod32((uint32_t)j.sp.mods[0].q, 4)});
         }
         if (j.kind == kJobResident && j.rp.kparts > 1) {
           j.rp.part_ws = (uint32_t*)p->d_part_ws + (uintptr_t)j.rp.part_ws;
-          p->sums.push_back({j.rp.part_ws, j.rp.c, j.rp.nprod * j.rp.n, j.rp.kparts, j.rp.mods[0]});
+          p->segs.push_back({j.rp.part_ws, j.rp.c, j.rp.nprod * j.rp.n, j.rp.kparts, 0, j.rp.mods[0]});
         }
+      }
+      uint64_t blocks = 0;
+      for (SplitSeg& sg : p->segs) {
+        sg.first_block = (uint32_t)blocks;
+        blocks += (sg.words / 4 + 255) / 256;
+      }
+      if (blocks > 0x7FFFFFFFull) { plan_free(p); return POLYMUL_EUNSUPPORTED; }
+      p->sum_blocks = (uint32_t)blocks;
+      if (hipMalloc((void**)&p->d_segs, p->segs.size() * sizeof(SplitSeg)) != hipSuccess) {
+        plan_free(p);
+        return POLYMUL_ENOMEM;
       }
     }
     hipError_t e = hipMemcpy(p->d_jobs, jobs.data(), jobs.size() * sizeof(GroupJob), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p->d_items, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !p->segs.empty())
+      e = hipMemcpy(p->d_segs, p->segs.data(), p->segs.size() * sizeof(SplitSeg), hipMemcpyHostToDevice);
+    // the grouped kernel leaves its counters at zero; they start there (set outside any capture)
+    if (e == hipSuccess) e = hipMemset(p->d_counter, 0, 2 * sizeof(uint32_t));
     if (e != hipSuccess) { plan_free(p); return hip_fail(e, "hipMemcpy (plan tables)"); }
     // persistent grid: as many workgroups as fit at once (two per CU within the register budget)
     const uint32_t per_cu = std::max(1u, std::min(2u, kMaxLds / std::max(p->lds, 1u)));

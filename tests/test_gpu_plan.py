@@ -127,3 +127,34 @@ def test_plan_split_k_runs():
             got = to_host(dc, np.uint32)
             assert np.array_equal(got, wv), f"replay {rep}, n={n}: " + mismatch_report(got, wv)
     plan.close()
+
+
+@pytest.mark.parametrize("flags", [0, pm.binding.POLYMUL_PLAN_NO_GRAPH])
+def test_plan_back_to_back_replays(flags):
+    """Replays queued back to back on one stream, two plans interleaved: each launch
+    leaves its queue counters at zero for the next, with no reset in between."""
+    rng = np.random.Generator(np.random.PCG64(31))
+    specs = [[(16384, 1068236801, 1), (256, 3329, 40), (1024, 65537, 6)], [(4096, (1 << 32) - 5, 3), (64, 17, 9)]]
+    plans, checks = [], []
+    for spec in specs:
+        groups, host = [], []
+        for n, q, count in spec:
+            a = rng.integers(0, q, size=(count, n), dtype=np.uint64).astype(np.uint32)
+            b = rng.integers(0, q, size=(count, n), dtype=np.uint64).astype(np.uint32)
+            da, db = to_dev(a), to_dev(b)
+            groups.append((da, db, torch.zeros_like(da), n, q))
+            host.append(oracle.negacyclic(a, b, q))
+        plans.append(pm.Plan(groups, flags))
+        checks.append((groups, host))
+    for rep in range(4):
+        for (groups, _), plan in zip(checks, plans):
+            for g in groups:
+                g[2].zero_()
+            plan.execute()
+    torch.cuda.synchronize()
+    for groups, host in checks:
+        for (_, _, dc, n, q), wv in zip(groups, host):
+            got = to_host(dc, np.uint32)
+            assert np.array_equal(got, wv), f"n={n}: " + mismatch_report(got, wv)
+    for plan in plans:
+        plan.close()
