@@ -78,14 +78,17 @@ __device__ __forceinline__ uint64_t neg_digits64(uint64_t x, const ModQ64& m) {
   return digits64<L>(x == 0 ? 0ull : m.q - x, m);
 }
 
-// Byte i of four packed digit words -> plane i, one dword per plane.
+// Byte i of four packed digit words -> plane i, one dword per plane: the byte
+// transpose of the resident kernel on the low words (planes 0-3) and, past
+// four limbs, on the high words (planes 4-7).
 template <int L>
 __device__ __forceinline__ void transpose_store64(uint8_t* base, uint32_t plane, uint32_t off, const uint64_t (&w)[4]) {
-#pragma unroll
-  for (int i = 0; i < L; ++i) {
-    const uint32_t v = (uint32_t)((w[0] >> (8 * i)) & 0xFF) | ((uint32_t)((w[1] >> (8 * i)) & 0xFF) << 8) |
-                       ((uint32_t)((w[2] >> (8 * i)) & 0xFF) << 16) | ((uint32_t)((w[3] >> (8 * i)) & 0xFF) << 24);
-    *(uint32_t*)(base + i * plane + off) = v;
+  const uint32_t lo[4] = {(uint32_t)w[0], (uint32_t)w[1], (uint32_t)w[2], (uint32_t)w[3]};
+  transpose_store<(L < 4 ? L : 4)>(base, plane, off, lo);
+  if constexpr (L > 4) {
+    const uint32_t hi[4] = {(uint32_t)(w[0] >> 32), (uint32_t)(w[1] >> 32), (uint32_t)(w[2] >> 32),
+                            (uint32_t)(w[3] >> 32)};
+    transpose_store<L - 4>(base + 4 * plane, plane, off, hi);
   }
 }
 
