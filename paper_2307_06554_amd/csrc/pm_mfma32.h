@@ -234,26 +234,6 @@ __device__ __forceinline__ void a_align(v4i (&a)[L], const uint32_t (&x)[L][5], 
     a[i][3] = (int)__builtin_amdgcn_alignbyte(x[i][4], x[i][3], sh);
   }
 }
-// One K-step of L*L MFMAs, B limb (column) by column.  As soon as column j is
-// issued, b[j] takes the next step's read for limb j, which then has the rest
-// of this step to land.  The reads are unconditional (the caller clamps the
-// address on the last step) so that the loop body has no branches and keeps
-// its registers in place.
-template <int L>
-__device__ __forceinline__ void mfma_step(v16i (&acc)[2 * L - 1], const v4i (&a)[L], v4i (&b)[L],
-                                          const uint8_t* bplane, uint32_t b_plane, int boff_next) {
-#pragma unroll
-  for (int j = 0; j < L; ++j) {
-#pragma unroll
-    for (int i = 0; i < L; ++i)
-      acc[i + j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], b[j], acc[i + j], 0, 0, 0);
-    b[j] = *(const v4i*)(bplane + j * b_plane + boff_next);
-    // keep each refill right behind its column: the scheduler would otherwise sink it
-    // to the next step's first use and expose the LDS latency
-    __builtin_amdgcn_sched_barrier(0);
-  }
-}
-
 // The same K-step with the next step's A fragments aligned in place during the
 // last column: right after the column's MFMA on limb i (the last to read a[i]),
 // a[i] takes limb i of the next step (its runs read a step earlier) and the raw
