@@ -819,8 +819,11 @@ polymul_status polymul_plan_create(polymul_plan** plan, const polymul_group* gro
     if (e == hipSuccess) e = hipMemcpy(p->d_items, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice);
     if (e == hipSuccess && !p->segs.empty())
       e = hipMemcpy(p->d_segs, p->segs.data(), p->segs.size() * sizeof(SplitSeg), hipMemcpyHostToDevice);
-    // the grouped kernel leaves its counters at zero; they start there (set outside any capture)
+    // the grouped kernel leaves its counters at zero; they start there (set outside any
+    // capture, and finished before the plan is returned: the caller's stream need not
+    // be ordered after the null stream the memset runs on)
     if (e == hipSuccess) e = hipMemset(p->d_counter, 0, 2 * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
     if (e != hipSuccess) { plan_free(p); return hip_fail(e, "hipMemcpy (plan tables)"); }
     // persistent grid: as many workgroups as fit at once (two per CU within the register budget)
     const uint32_t per_cu = std::max(1u, std::min(2u, kMaxLds / std::max(p->lds, 1u)));
