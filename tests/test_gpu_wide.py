@@ -70,6 +70,31 @@ def test_u64_worst_case_digits_flush():
     _check64(a, a, GOLD)
 
 
+@pytest.mark.parametrize("sign", ["pos", "neg"])
+def test_streaming_flush_extreme_class_sums(sign):
+    """Every digit +127 (words 0x7F..7F, the window's top) against every digit +127 or
+    words whose digits are mostly -128: the shift-class sums reach their largest
+    magnitude within each flush interval, for 8 limbs (64-bit q) and 4 limbs (32-bit
+    q, streamed above n = 8192).  The flush adds the classes four at a time into
+    64-bit sums offset by 2^56 and removes the offset with a precomputed constant."""
+    top8 = np.uint64(0x7F7F7F7F7F7F7F7F)
+    # one past the window's top is stored as x - q: digits 127 x4, -128 x4 for this q
+    other8 = top8 if sign == "pos" else np.uint64(0x7F7F7F7F7F7F7F80)
+    n = 16384
+    a = np.full((1, n), top8, dtype=np.uint64)
+    b = np.full((1, n), other8, dtype=np.uint64)
+    _check64(a, b, GOLD)
+    q32 = (1 << 32) - 5
+    top4 = np.uint32(0x7F7F7F7F)
+    other4 = top4 if sign == "pos" else np.uint32(0x7F7F7F80)  # digits -123, -128, -128, -128
+    n = 32768
+    a = np.full((1, n), top4, dtype=np.uint32)
+    b = np.full((1, n), other4, dtype=np.uint32)
+    want = oracle.negacyclic(a, b, q32)
+    got = to_host(pm.polymul_negacyclic(to_dev(a), to_dev(b), q32), np.uint32)
+    assert np.array_equal(got, want), mismatch_report(got, want)
+
+
 @pytest.mark.parametrize("n", [16384, 32768, 65536])
 @pytest.mark.parametrize("q", [1068236801, (1 << 32) - 5])
 def test_u32_streaming_large_degree(n, q):
