@@ -33,17 +33,19 @@ struct CrtConsts {
   uint32_t magic[kMaxCh];      // floor(2^32 / m)
   uint32_t off[kMaxCh];        // 2^31 mod m
   uint32_t y[kMaxCh];          // (M / m)^-1 mod m
+  uint32_t yp[kMaxCh];         // floor(y 2^32 / m): Shoup's companion of y
+  uint32_t oy[kMaxCh];         // (2^31 y) mod m
   float invm[kMaxCh];          // 1 / m
   uint32_t w[kMaxQC][kMaxCh];  // (M / m) mod q
   uint32_t Mq[kMaxQC];         // M mod q
 };
 
-// w mod m for a 32-bit w (two corrections cover the Barrett undershoot).
+// w mod m for a 32-bit w: with magic = floor(2^32 / m) the quotient estimate is
+// floor(w / m) or one less (as for the word reduction mod q), so one conditional
+// subtraction ends it.
 __device__ __forceinline__ uint32_t small_mod(uint32_t w, uint32_t m, uint32_t magic) {
-  uint32_t r = w - __umulhi(w, magic) * m;
-  if (r >= m) r -= m;
-  if (r >= m) r -= m;
-  return r;
+  const uint32_t r = w - __umulhi(w, magic) * m;
+  return min(r, r - m);
 }
 // v mod m in [0, m) for a signed v, |v| < 2^31.
 __device__ __forceinline__ uint32_t signed_mod(int32_t v, uint32_t m, uint32_t magic, uint32_t off) {
@@ -201,31 +203,52 @@ __device__ __forceinline__ void crt_tile(const Mfma32Params& P, const uint8_t* a
                 B_of(st));
 }
 
-// Reconstruction of the 16 outputs a lane holds, then the stores.
+// Reconstruction of the 16 outputs a lane holds, then the stores.  Per channel,
+// s = (T mod m) y mod m is one Shoup product: for the 32-bit word T + 2^31 and
+// y < m, (T + 2^31) y - floor((T + 2^31) yp / 2^32) m lies in [0, 2m), and the
+// precomputed (2^31 y) mod m removes the offset.  The running sum
+// lift + sum_c s w_c - kappa (M mod q) stays in (2^62 - 2^36, 2^62 + 2^44 + q).
 template <int C>
 __device__ __forceinline__ void crt_epilogue(const Mfma32Params& P, const CrtConsts& K, uint64_t gprod, uint32_t li,
                                              int z0, int u0, const v16i (&acc)[C]) {
-  const ModQ32& m = P.mods[li];
+  const ModQ32 m = P.mods[li];
   const int lane = threadIdx.x & 63;
   const int g = lane >> 5;
   const int u = u0 + (lane & 31);
-  uint32_t out[16];
+  uint32_t mc[C], yv[C], yp[C], oy[C], wv[C];
+  float im[C];
 #pragma unroll
-  for (int rr = 0; rr < 16; ++rr) {
-    float f = 0.0f;
-    int64_t x = 0;
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-      const uint32_t mc = K.m[c];
-      const uint32_t t = signed_mod(acc[c][rr], mc, K.magic[c], K.off[c]);
-      const uint32_t s = small_mod(t * K.y[c], mc, K.magic[c]);
-      f += (float)s * K.invm[c];
-      x += (int64_t)s * (int64_t)K.w[li][c];
-    }
-    const int32_t kappa = (int32_t)floorf(f + 0.5f);
-    x -= (int64_t)kappa * (int64_t)K.Mq[li];
-    out[rr] = reduce_i64(x, m);
+  for (int c = 0; c < C; ++c) {
+    mc[c] = K.m[c];
+    yv[c] = K.y[c];
+    yp[c] = K.yp[c];
+    oy[c] = K.oy[c];
+    wv[c] = K.w[li][c];
+    im[c] = K.invm[c];
   }
+  const uint32_t Mq = K.Mq[li];
+  uint32_t out[16];
+  auto reconstruct = [&](auto reduce) {
+#pragma unroll
+    for (int rr = 0; rr < 16; ++rr) {
+      float f = 0.0f;
+      uint64_t x = m.lift;
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const uint32_t tu = (uint32_t)acc[c][rr] + 0x80000000u;
+        uint32_t su = tu * yv[c] - __umulhi(tu, yp[c]) * mc[c];
+        su = min(su, su - mc[c]);
+        const uint32_t sc = su >= oy[c] ? su - oy[c] : su + mc[c] - oy[c];
+        f += (float)sc * im[c];
+        x += (uint64_t)sc * wv[c];
+      }
+      const uint32_t kappa = (uint32_t)floorf(f + 0.5f);
+      x -= (uint64_t)kappa * Mq;
+      out[rr] = reduce(x);
+    }
+  };
+  if (m.q < 0x80000000u) reconstruct([&](uint64_t x) { return reduce_u64_q31(x, m.mu, m.q); });
+  else reconstruct([&](uint64_t x) { return reduce_u64(x, m); });
   if (u >= (int)P.r) return;
   uint32_t* Cout = P.c + gprod * P.n;
 #pragma unroll

@@ -309,6 +309,8 @@ polymul_status fill_crt(CrtConsts& K, const uint32_t* qs, uint32_t lc, uint64_t 
       if ((uint64_t)r * k % mc == 1) { y = k; break; }
     if (y == 0 && mc > 1) return POLYMUL_EDEVICE;  // unreachable for co-prime moduli
     K.y[c] = y;
+    K.yp[c] = (uint32_t)(((uint64_t)y << 32) / mc);
+    K.oy[c] = (uint32_t)(((uint64_t)1 << 31) * y % mc);
     K.magic[c] = (uint32_t)((1ull << 32) / mc);
     K.off[c] = (uint32_t)((1ull << 31) % mc);
     K.invm[c] = 1.0f / (float)mc;
