@@ -704,9 +704,9 @@ polymul_status polymul_plan_create(polymul_plan** plan, const polymul_group* gro
   std::vector<WorkItem> items;
   // Balance (paper Sec. 3 notes the TPU's lack of fine control): the persistent grid
   // holds two workgroups per CU; the items of a 32-bit group that would cost more
-  // than an even share of the total have their K range cut into runs (resident
-  // groups of one product, or streamed blocks), whose residues a second kernel
-  // adds up mod q.
+  // than a CU's even share of the total (two workgroups' shares: finer runs pay more
+  // staging than they save) have their K range cut into runs (resident groups of one
+  // product, or streamed blocks), whose residues a second kernel adds up mod q.
   uint64_t total_cost = 0;
   for (uint32_t g = 0; g < ngroups; ++g) {
     if (groups[g].elem_bytes != 4 || groups[g].count == 0) continue;
@@ -714,7 +714,7 @@ polymul_status polymul_plan_create(polymul_plan** plan, const polymul_group* gro
     default_cost((uint32_t)groups[g].n, groups[g].count, &ni, &ci);
     total_cost += ni * ci;
   }
-  const uint64_t share = std::max<uint64_t>(64, total_cost / (2ull * device_cus()));
+  const uint64_t share = std::max<uint64_t>(64, total_cost / device_cus());
   uint64_t part_words = 0;
   for (uint32_t g = 0; g < ngroups; ++g) {
     const polymul_group& G = groups[g];
