@@ -111,7 +111,7 @@ __device__ __forceinline__ uint32_t neg_digits32(uint32_t x, uint32_t q, uint32_
   return digits32<L>(x == 0 ? 0u : q - x, q, thr);
 }
 // Both digit words of residues x in [0, q): of x and of a representative of -x.
-// When q <= thr (every modulus below the window's top, e.g. q < 2^31 for L = 4)
+// When q <= thr (the window's top: 0x7F7F7F7F for L = 4, so every 30-bit q)
 // x and q - x are in the window as they are; q - 0 = q stands for 0.
 // Four residues at a time, the window test taken once.
 template <int L>
