@@ -150,8 +150,8 @@ def main():
                     help="first copy this many MiB device-to-device (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the products are independent and this build has no "
-              "multi-GPU path (DESIGN.md describes how it would shard). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only: the products are independent and this library has no "
+              "multi-GPU path (each GPU would take its own share of the products). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

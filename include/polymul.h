@@ -43,7 +43,7 @@ typedef enum {
     POLYMUL_OK = 0,
     POLYMUL_EINVAL = 1,        /* bad n, q, L, count, null pointer or size overflow */
     POLYMUL_EALIAS = 2,        /* c overlaps a or b */
-    POLYMUL_EUNSUPPORTED = 3,  /* valid arguments outside what this build implements */
+    POLYMUL_EUNSUPPORTED = 3,  /* valid arguments outside what this library implements */
     POLYMUL_ENOMEM = 4,        /* device or host allocation failed (plans only) */
     POLYMUL_EDEVICE = 5        /* a HIP call or kernel launch failed */
 } polymul_status;
