@@ -50,6 +50,20 @@ def measured_traffic():
     return rec.get("hbm_bytes_per_launch")
 
 
+def measured_mfma_busy():
+    """Share of the dominant kernel's cycles with its MFMA units busy, from the committed
+    rocprofv3 counter summary, only if it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "counters_mfma_lds_n4096_rns8.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("csrc_hash") != csrc_hash():
+        return None
+    return rec.get("mfma_busy")
+
+
 def time_steps(fn, steps, warmup):
     """Average milliseconds per step, events on the launch stream (torch's current)."""
     import torch
@@ -252,7 +266,7 @@ def main():
         "config": {"workload": w.name, "n": n, "rns_channels": L, "pairs": B, "products_per_step": products,
                    "q_bits": 30, "limbs": limbs, "tile_t": pm.polymul_tune_get(n, limbs), "tune_cache": tuned},
         "roofline": {"bound": "mfma", "achieved": achieved_tops, "peak": PEAK_INT8_TOPS, "unit": "TFLOP/s",
-                     "frac": achieved_tops / PEAK_INT8_TOPS, "traffic": measured_traffic(), "kernel": KERNEL},
+                     "frac": achieved_tops / PEAK_INT8_TOPS, "traffic": measured_traffic(), "mfma_busy": measured_mfma_busy(), "kernel": KERNEL},
         "karatsuba": kara,
         "shared_operand": shared,
         "rns_crt": crt,
