@@ -15,6 +15,7 @@ import argparse
 import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -64,6 +65,26 @@ def measured_mfma_busy():
     return rec.get("mfma_busy")
 
 
+def preheat(fn, seconds):
+    """Run fn (untimed) for at least `seconds` of wall clock; returns (launches, seconds).
+    The shader clock of a cold GPU takes a few hundred launches of this kernel to
+    settle, more than a handful of warm-up steps cover."""
+    import torch
+    if seconds <= 0:
+        return 0, 0.0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    k = 0
+    while True:
+        for _ in range(8):
+            fn()
+        k += 8
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if dt >= seconds:
+            return k, dt
+
+
 def time_steps(fn, steps, warmup):
     """Average milliseconds per step, events on the launch stream (torch's current)."""
     import torch
@@ -81,8 +102,22 @@ def time_steps(fn, steps, warmup):
     return e0.elapsed_time(e1) / steps
 
 
-def cpu_baseline(w, budget_s):
-    """The oracle, as it is, on a bounded sample of the same workload."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(w, budget_s, c_gpu):
+    """The oracle, as it is, on the host cores: best of up to three runs over a
+    bounded sample of the same workload (all pairs when they fit the budget).  The
+    sample's oracle results are also compared word for word with c_gpu, the output
+    of the timed GPU launch; returns (baseline, parity)."""
     import numpy as np
     import oracle
     B, L, n = w.a.shape
@@ -91,18 +126,31 @@ def cpu_baseline(w, budget_s):
     oracle.negacyclic_rns(w.a[:1], w.b[:1], w.qs)  # one pair = L products, also the calibration
     per_pair = time.perf_counter() - t0
     pairs = int(max(1, min(B, budget_s / max(per_pair, 1e-6))))
-    t0 = time.perf_counter()
-    oracle.negacyclic_rns(w.a[:pairs], w.b[:pairs], w.qs)
-    dt = time.perf_counter() - t0
+    times = []
+    mismatches = None
+    while len(times) < 3:
+        t0 = time.perf_counter()
+        want = oracle.negacyclic_rns(w.a[:pairs], w.b[:pairs], w.qs)
+        times.append(time.perf_counter() - t0)
+        if mismatches is None:
+            mismatches = int(np.count_nonzero(want != c_gpu[:pairs]))
+        if sum(times) + times[-1] > budget_s:
+            break
+    dt = min(times)
     # one thread on one product (one channel of one pair), for the per-core rate
     prev = oracle.set_threads(1)
     t1 = time.perf_counter()
     oracle.negacyclic(w.a[:1, 0], w.b[:1, 0], w.qs[0])
     dt1 = time.perf_counter() - t1
     oracle.set_threads(prev)
-    return {"value": pairs * L / dt, "unit": "polymuls/s", "cores": cores, "kind": "oracle",
-            "sample": f"{pairs} of {B} ciphertext pairs x {L} channels (n={n}, 30-bit q), {dt:.1f} s wall",
-            "single_thread_value": 1 / dt1}
+    base = {"value": pairs * L / dt, "unit": "polymuls/s", "cores": cores, "kind": "oracle",
+            "sample": f"{pairs} of {B} ciphertext pairs x {L} channels (n={n}, 30-bit q), best of "
+                      f"{len(times)} runs: " + ", ".join(f"{t:.2f}" for t in times) + " s wall",
+            "cpu_model": cpu_model(), "single_thread_value": 1 / dt1}
+    parity = {"reference": "CPU oracle (schoolbook, 128-bit sums)", "checked_products": pairs * L,
+              "of_products": B * L, "checked_words": pairs * L * n, "mismatches": mismatches,
+              "bit_exact": mismatches == 0}
+    return base, parity
 
 
 def other_workloads(steps, warmup):
@@ -156,7 +204,10 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=150,
                     help="untimed steps; the shader clock settles within about 100 launches")
-    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for cpu_baseline")
+    ap.add_argument("--cpu-budget", type=float, default=24.0,
+                    help="seconds of oracle work for cpu_baseline (and the parity check of the timed output)")
+    ap.add_argument("--preheat-s", type=float, default=1.0,
+                    help="untimed seconds of the headline launch before its warm-up steps (clock settling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--all", action="store_true", help="also time the other workloads (stderr)")
     ap.add_argument("--karatsuba-depth", type=int, default=2, help="0 skips the Karatsuba route")
@@ -191,8 +242,11 @@ def main():
     b = torch.from_numpy(w.b.view(np.int32)).to(dev)
     c = torch.empty_like(a)
 
-    ms = time_steps(lambda: pm.polymul_negacyclic_rns(a, b, w.qs, out=c), args.steps, args.warmup)
+    headline = lambda: pm.polymul_negacyclic_rns(a, b, w.qs, out=c)
+    pre_launches, pre_s = preheat(headline, args.preheat_s)
+    ms = time_steps(headline, args.steps, args.warmup)
     value = products / (ms / 1e3)
+    c_timed = c.cpu().numpy().view(np.uint32).copy()  # output of the timed launches
 
     # the plain integer kernel on the same inputs, one channel at a time (same total work);
     # channel slices are copied once up front so the timed region holds only that kernel
@@ -257,6 +311,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "preheat": {"launches": pre_launches, "seconds": round(pre_s, 3)},
         "ms_per_step": ms,
         "higher_is_better": True,
         "scaling": "weak",
@@ -265,7 +320,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "n": n, "rns_channels": L, "pairs": B, "products_per_step": products,
                    "q_bits": 30, "limbs": limbs, "tile_t": pm.polymul_tune_get(n, limbs), "tune_cache": tuned},
-        "roofline": {"bound": "mfma", "achieved": achieved_tops, "peak": PEAK_INT8_TOPS, "unit": "TFLOP/s",
+        "roofline": {"bound": "mfma", "achieved": achieved_tops, "peak": PEAK_INT8_TOPS, "unit": "TOPS",
                      "frac": achieved_tops / PEAK_INT8_TOPS, "traffic": measured_traffic(), "mfma_busy": measured_mfma_busy(), "kernel": KERNEL},
         "karatsuba": kara,
         "shared_operand": shared,
@@ -273,12 +328,17 @@ def main():
         "plain_int": {"value": plain_value, "unit": "polymuls/s", "ms_per_step": ms_plain,
                       "mfma_speedup": value / plain_value},
     }
+    out["parity"] = None
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
+        out["cpu_baseline"], out["parity"] = cpu_baseline(w, args.cpu_budget, c_timed)
     if args.all:
         print(json.dumps({"other_workloads": other_workloads(max(20, args.steps // 4), 20)}), file=sys.stderr,
               flush=True)
     print(json.dumps(out), flush=True)
+    if out["parity"] is not None and out["parity"]["mismatches"]:
+        print(f"bench.py: the timed output differs from the oracle in {out['parity']['mismatches']} words",
+              file=sys.stderr)
+        sys.exit(1)
 
 
 if __name__ == "__main__":

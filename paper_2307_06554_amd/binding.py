@@ -105,16 +105,44 @@ def _words(t, nbytes, name):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def polymul_negacyclic(a, b, q, out=None, stream=None):
-    """c = a*b in Z_q[x]/(x^n+1) for 32-bit words [..., n], q < 2^32 (int8-MFMA path)."""
+def _result(out, like, nbytes, name="out"):
+    """`out` checked against the result it must hold (the shape of `like`, words of
+    `nbytes` bytes), or a new tensor like `like`.  The C ABI carries no buffer
+    sizes, so an undersized output would be written past its end: refuse it here."""
     import torch
+    if out is None:
+        return torch.empty_like(like)
+    if not isinstance(out, torch.Tensor):
+        raise TypeError(f"{name} must be a tensor")
+    if tuple(out.shape) != tuple(like.shape):
+        raise ValueError(f"{name} has shape {tuple(out.shape)}, the result needs {tuple(like.shape)}")
+    if out.element_size() != nbytes or out.is_floating_point() or out.is_complex():
+        raise ValueError(f"{name} must hold {8 * nbytes}-bit integer words")
+    return out
+
+
+def _pair(a, b):
+    """a and b of one shape [..., n]; returns (n, batch)."""
     if a.shape != b.shape or a.dim() < 1:
         raise ValueError("a and b must have the same shape [..., n]")
     n = a.shape[-1]
-    batch = a.numel() // n if n else 0
-    c = torch.empty_like(a) if out is None else out
-    if c.shape != a.shape:
-        raise ValueError("out has the wrong shape")
+    return n, (a.numel() // n if n else 0)
+
+
+def _rns_shape(a, b, qs):
+    """a and b of one shape [batch, L, n] with one modulus per channel; returns (batch, L, n)."""
+    if a.shape != b.shape or a.dim() != 3:
+        raise ValueError("a and b must be [batch, L, n]")
+    batch, L, n = a.shape
+    if len(qs) != L:
+        raise ValueError("need one modulus per channel")
+    return batch, L, n
+
+
+def polymul_negacyclic(a, b, q, out=None, stream=None):
+    """c = a*b in Z_q[x]/(x^n+1) for 32-bit words [..., n], q < 2^32 (int8-MFMA path)."""
+    n, batch = _pair(a, b)
+    c = _result(out, a, 4)
     st = load_library().polymul_negacyclic(_words(a, 4, "a"), _words(b, 4, "b"), _words(c, 4, "out"),
                                           n, int(q), batch, _stream(stream))
     _check(st, "polymul_negacyclic")
@@ -123,12 +151,8 @@ def polymul_negacyclic(a, b, q, out=None, stream=None):
 
 def polymul_negacyclic_plain(a, b, q, out=None, stream=None):
     """Same product with the plain integer schoolbook kernel (baseline)."""
-    import torch
-    if a.shape != b.shape or a.dim() < 1:
-        raise ValueError("a and b must have the same shape [..., n]")
-    n = a.shape[-1]
-    batch = a.numel() // n if n else 0
-    c = torch.empty_like(a) if out is None else out
+    n, batch = _pair(a, b)
+    c = _result(out, a, 4)
     st = load_library().polymul_negacyclic_plain(_words(a, 4, "a"), _words(b, 4, "b"), _words(c, 4, "out"),
                                                 n, int(q), batch, _stream(stream))
     _check(st, "polymul_negacyclic_plain")
@@ -137,12 +161,8 @@ def polymul_negacyclic_plain(a, b, q, out=None, stream=None):
 
 def polymul_negacyclic_u64(a, b, q, out=None, stream=None):
     """c = a*b in Z_q[x]/(x^n+1) for 64-bit words [..., n], q < 2^64."""
-    import torch
-    if a.shape != b.shape or a.dim() < 1:
-        raise ValueError("a and b must have the same shape [..., n]")
-    n = a.shape[-1]
-    batch = a.numel() // n if n else 0
-    c = torch.empty_like(a) if out is None else out
+    n, batch = _pair(a, b)
+    c = _result(out, a, 8)
     st = load_library().polymul_negacyclic_u64(_words(a, 8, "a"), _words(b, 8, "b"), _words(c, 8, "out"),
                                               n, int(q), batch, _stream(stream))
     _check(st, "polymul_negacyclic_u64")
@@ -150,14 +170,8 @@ def polymul_negacyclic_u64(a, b, q, out=None, stream=None):
 
 
 def _binary(name, a, b, q, out, stream, nbytes):
-    import torch
-    if a.shape != b.shape or a.dim() < 1:
-        raise ValueError("a and b must have the same shape [..., n]")
-    n = a.shape[-1]
-    batch = a.numel() // n if n else 0
-    c = torch.empty_like(a) if out is None else out
-    if c.shape != a.shape:
-        raise ValueError("out has the wrong shape")
+    n, batch = _pair(a, b)
+    c = _result(out, a, nbytes)
     st = getattr(load_library(), name)(_words(a, nbytes, "a"), _words(b, nbytes, "b"), _words(c, nbytes, "out"),
                                        n, int(q), batch, _stream(stream))
     _check(st, name)
@@ -176,13 +190,8 @@ def polymul_cyclic_u64(a, b, q, out=None, stream=None):
 
 def polymul_negacyclic_rns(a, b, qs, out=None, stream=None):
     """RNS form: a, b are 32-bit words [batch, L, n]; channel l is taken mod qs[l]."""
-    import torch
-    if a.shape != b.shape or a.dim() != 3:
-        raise ValueError("a and b must be [batch, L, n]")
-    batch, L, n = a.shape
-    if len(qs) != L:
-        raise ValueError("need one modulus per channel")
-    c = torch.empty_like(a) if out is None else out
+    batch, L, n = _rns_shape(a, b, qs)
+    c = _result(out, a, 4)
     qarr = (ctypes.c_uint32 * L)(*[int(x) for x in qs])
     st = load_library().polymul_negacyclic_rns(_words(a, 4, "a"), _words(b, 4, "b"), _words(c, 4, "out"),
                                               n, ctypes.cast(qarr, ctypes.c_void_p), L, batch, _stream(stream))
@@ -197,13 +206,8 @@ def polymul_negacyclic_crt(a, b, q, out=None, stream=None):
 
 def polymul_negacyclic_rns_crt(a, b, qs, out=None, stream=None):
     """RNS form [batch, L, n] of polymul_negacyclic_crt; channel l is taken mod qs[l]."""
-    import torch
-    if a.shape != b.shape or a.dim() != 3:
-        raise ValueError("a and b must be [batch, L, n]")
-    batch, L, n = a.shape
-    if len(qs) != L:
-        raise ValueError("need one modulus per channel")
-    c = torch.empty_like(a) if out is None else out
+    batch, L, n = _rns_shape(a, b, qs)
+    c = _result(out, a, 4)
     qarr = (ctypes.c_uint32 * L)(*[int(x) for x in qs])
     st = load_library().polymul_negacyclic_rns_crt(_words(a, 4, "a"), _words(b, 4, "b"), _words(c, 4, "out"),
                                                   n, ctypes.cast(qarr, ctypes.c_void_p), L, batch, _stream(stream))
@@ -220,14 +224,11 @@ def polymul_crt_moduli(n, q):
 
 
 def _shared(name, a, b, q, out, stream, nbytes):
-    import torch
     if a.dim() < 1 or b.dim() != 1 or b.shape[0] != a.shape[-1]:
         raise ValueError("a must be [..., n] and b [n]")
     n = a.shape[-1]
     batch = a.numel() // n if n else 0
-    c = torch.empty_like(a) if out is None else out
-    if c.shape != a.shape:
-        raise ValueError("out has the wrong shape")
+    c = _result(out, a, nbytes)
     st = getattr(load_library(), name)(_words(a, nbytes, "a"), _words(b, nbytes, "b"), _words(c, nbytes, "out"),
                                        n, int(q), batch, _stream(stream))
     _check(st, name)
@@ -246,13 +247,12 @@ def polymul_negacyclic_u64_shared(a, b, q, out=None, stream=None):
 
 def polymul_negacyclic_rns_shared(a, b, qs, out=None, stream=None):
     """RNS form with one b per channel: a is [batch, L, n], b is [L, n]."""
-    import torch
     if a.dim() != 3 or b.dim() != 2 or b.shape != a.shape[1:]:
         raise ValueError("a must be [batch, L, n] and b [L, n]")
     batch, L, n = a.shape
     if len(qs) != L:
         raise ValueError("need one modulus per channel")
-    c = torch.empty_like(a) if out is None else out
+    c = _result(out, a, 4)
     qarr = (ctypes.c_uint32 * L)(*[int(x) for x in qs])
     st = load_library().polymul_negacyclic_rns_shared(_words(a, 4, "a"), _words(b, 4, "b"), _words(c, 4, "out"),
                                                      n, ctypes.cast(qarr, ctypes.c_void_p), L, batch,
@@ -273,12 +273,8 @@ def polymul_negacyclic_rns_karatsuba(a, b, qs, depth, workspace=None, out=None, 
     """polymul_negacyclic_rns through `depth` Karatsuba levels.  workspace: a device
     tensor of at least polymul_karatsuba_workspace_size bytes (allocated here if None)."""
     import torch
-    if a.shape != b.shape or a.dim() != 3:
-        raise ValueError("a and b must be [batch, L, n]")
-    batch, L, n = a.shape
-    if len(qs) != L:
-        raise ValueError("need one modulus per channel")
-    c = torch.empty_like(a) if out is None else out
+    batch, L, n = _rns_shape(a, b, qs)
+    c = _result(out, a, 4)
     need = polymul_karatsuba_workspace_size(n, L, batch, depth)
     if workspace is None:
         workspace = torch.empty(max(need, 16), dtype=torch.uint8, device=a.device)
@@ -302,11 +298,8 @@ def polymul_karatsuba_u64_workspace_size(n, batch, depth):
 def polymul_negacyclic_u64_karatsuba(a, b, q, depth, workspace=None, out=None, stream=None):
     """polymul_negacyclic_u64 through `depth` Karatsuba levels (64-bit words [..., n])."""
     import torch
-    if a.shape != b.shape or a.dim() < 1:
-        raise ValueError("a and b must have the same shape [..., n]")
-    n = a.shape[-1]
-    batch = a.numel() // n if n else 0
-    c = torch.empty_like(a) if out is None else out
+    n, batch = _pair(a, b)
+    c = _result(out, a, 8)
     need = polymul_karatsuba_u64_workspace_size(n, batch, depth)
     if workspace is None:
         workspace = torch.empty(max(need, 16), dtype=torch.uint8, device=a.device)
@@ -323,7 +316,15 @@ def polymul_plan_create(groups, flags=0):
     arr = (_Group * max(1, len(groups)))()
     for i, (a, b, c, n, q) in enumerate(groups):
         eb = a.element_size()
-        count = a.numel() // n if n else 0
+        if eb not in (4, 8):
+            raise ValueError(f"group {i}: words must be 32 or 64 bits")
+        if int(n) < 1 or a.numel() % int(n):
+            raise ValueError(f"group {i}: a does not hold whole polynomials of degree bound {n}")
+        if b.shape != a.shape or c.shape != a.shape:
+            raise ValueError(f"group {i}: a, b and c must have the same shape")
+        if b.element_size() != eb or c.element_size() != eb:
+            raise ValueError(f"group {i}: a, b and c must hold words of the same size")
+        count = a.numel() // n
         arr[i] = _Group(_words(a, eb, "a").value, _words(b, eb, "b").value, _words(c, eb, "c").value,
                         int(n), int(q), int(count), eb)
     handle = ctypes.c_void_p()

@@ -82,7 +82,8 @@ __device__ __forceinline__ void transpose_store(uint8_t* base, uint32_t plane, u
   }
 }
 
-// Stage the digit planes of one product into an LDS slot.
+// Stage the digit planes of one product of degree bound n < 4 into an LDS slot,
+// byte by byte (larger degrees are staged a word group at a time, below).
 //   A: reversed ext planes, position p holds ext[E - p] (ext[i] = a_i for i >= 0,
 //      -a_{n+i} for i < 0, zero outside (-n, n)).
 //   B: rows v in [v_lo, v_lo + b_rows): row v < r holds b[v t + w] for v >= 0 and
@@ -97,80 +98,6 @@ __device__ __forceinline__ void mfma32_stage(const Mfma32Params& P, uint8_t* slo
   const int a_dw = (int)(P.a_plane >> 2);
   uint8_t* bbase = slot + L * P.a_plane;
   const int row_dw = (int)(P.rowlen >> 2);
-  if (n >= 4) {
-    // E + 1 is a multiple of 4, so dword dw holds ext[4m .. 4m+3] reversed, m = (E+1)/4 - 1 - dw,
-    // and (since n is a multiple of 4) each group is wholly positive, negative or zero.
-    // All global loads of a pass are issued before any of them is used.
-    constexpr int kUnroll = 4;
-    const int mtop = (int)((P.E + 1) >> 2) - 1;
-    for (int base = 0; base < a_dw; base += kUnroll * kThreads) {
-      uint4 x[kUnroll];
-      int kind[kUnroll];
-#pragma unroll
-      for (int k = 0; k < kUnroll; ++k) {
-        const int dw = base + k * kThreads + (int)threadIdx.x;
-        const int i0 = 4 * (mtop - dw);
-        kind[k] = 0;
-        x[k] = make_uint4(0, 0, 0, 0);
-        if (dw < a_dw) {
-          if (i0 >= 0 && i0 < n) { kind[k] = 1; x[k] = *(const uint4*)(A + i0); }
-          else if (i0 < 0 && i0 >= -n) { kind[k] = 2; x[k] = *(const uint4*)(A + n + i0); }
-        }
-      }
-#pragma unroll
-      for (int k = 0; k < kUnroll; ++k) {
-        const int dw = base + k * kThreads + (int)threadIdx.x;
-        if (dw >= a_dw) continue;
-        const uint32_t xr[4] = {reduce_u32(x[k].w, m), reduce_u32(x[k].z, m), reduce_u32(x[k].y, m),
-                                reduce_u32(x[k].x, m)};
-        uint32_t w[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-          w[j] = kind[k] == 1 ? digits32<L>(xr[j], q, thr) : kind[k] == 2 ? neg_digits32<L>(xr[j], q, thr) : 0u;
-        transpose_store<L>(slot, P.a_plane, dw * 4, w);
-      }
-    }
-    // Source rows: each b word lands in row vs (+) and row vs - r (-) when staged.
-    const int src = r * row_dw;
-    for (int base = 0; base < src; base += kUnroll * kThreads) {
-      uint4 x[kUnroll];
-#pragma unroll
-      for (int k = 0; k < kUnroll; ++k) {
-        const int e = base + k * kThreads + (int)threadIdx.x;
-        const int vs = e / row_dw, wd = e - vs * row_dw;
-        x[k] = make_uint4(0, 0, 0, 0);
-        if (e < src && 4 * wd < t) x[k] = *(const uint4*)(B + vs * t + 4 * wd);
-      }
-#pragma unroll
-      for (int k = 0; k < kUnroll; ++k) {
-        const int e = base + k * kThreads + (int)threadIdx.x;
-        if (e >= src) continue;
-        const int vs = e / row_dw, wd = e - vs * row_dw;
-        const int rp = vs - v_lo, rn = vs - r - v_lo;
-        const uint32_t xr[4] = {reduce_u32(x[k].x, m), reduce_u32(x[k].y, m), reduce_u32(x[k].z, m),
-                                reduce_u32(x[k].w, m)};
-        uint32_t w[4], nw[4];
-        const bool live = 4 * wd < t;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          w[j] = live ? digits32<L>(xr[j], q, thr) : 0u;
-          nw[j] = live ? neg_digits32<L>(xr[j], q, thr) : 0u;
-        }
-        if (rp >= 0 && rp < (int)P.b_rows) transpose_store<L>(bbase, P.b_plane, rp * P.b_rowstride + wd * 4, w);
-        if (rn >= 0 && rn < (int)P.b_rows) transpose_store<L>(bbase, P.b_plane, rn * P.b_rowstride + wd * 4, nw);
-      }
-    }
-    // Zero rows past the product (v >= r) inside the staged range.
-    const int z0 = max(0, r - v_lo);
-    const int nz = ((int)P.b_rows - z0) * row_dw;
-    for (int e = threadIdx.x; e < nz; e += blockDim.x) {
-      const int row = z0 + e / row_dw, wd = e % row_dw;
-      const uint32_t w[4] = {0, 0, 0, 0};
-      transpose_store<L>(bbase, P.b_plane, row * P.b_rowstride + wd * 4, w);
-    }
-    return;
-  }
-  // n < 4: byte-wise staging.
   for (int dw = threadIdx.x; dw < a_dw; dw += blockDim.x) {
     uint32_t w[4];
 #pragma unroll
