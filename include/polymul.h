@@ -45,7 +45,8 @@ typedef enum {
     POLYMUL_EALIAS = 2,        /* c overlaps a or b */
     POLYMUL_EUNSUPPORTED = 3,  /* valid arguments outside what this library implements */
     POLYMUL_ENOMEM = 4,        /* device or host allocation failed (plans only) */
-    POLYMUL_EDEVICE = 5        /* a HIP call or kernel launch failed */
+    POLYMUL_EDEVICE = 5,       /* a HIP call or kernel launch failed */
+    POLYMUL_ESCRATCH = 6       /* needs more than the library's own scratch (allocation-free call) */
 } polymul_status;
 
 /* Human-readable name of a status code (static storage, never NULL). */
@@ -226,6 +227,27 @@ polymul_status polymul_negacyclic_rns_karatsuba(const uint32_t* a, const uint32_
                                                 uint64_t n, const uint32_t* q, uint32_t L,
                                                 uint64_t batch, uint32_t depth, void* workspace,
                                                 uint64_t workspace_bytes, hipStream_t stream);
+
+/*
+ * polymul_negacyclic_rns_karatsuba for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the workspace is not an argument but a buffer of
+ * POLYMUL_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs on,
+ * set aside when the library's code is loaded on that GPU and kept until the
+ * process ends.  The call itself allocates nothing.
+ *   a, b, c, n, q, L, batch, depth: as for polymul_negacyclic_rns_karatsuba;
+ *   same results, word for word.
+ * Every call on one GPU uses that GPU's one buffer: calls that may overlap in
+ * time on one GPU (unordered streams, host threads) race and give wrong results;
+ * order them on one stream.  The buffer's contents on entry do not matter.
+ * Errors: as polymul_negacyclic_rns_karatsuba, and POLYMUL_ESCRATCH when the
+ * call needs more than POLYMUL_NOALLOC_SCRATCH_BYTES of workspace (as sized by
+ * polymul_karatsuba_workspace_size); split such a batch.
+ */
+#define POLYMUL_NOALLOC_SCRATCH_BYTES (64ull << 20)
+polymul_status polymul_negacyclic_rns_karatsuba_noalloc(const uint32_t* a, const uint32_t* b, uint32_t* c,
+                                                        uint64_t n, const uint32_t* q, uint32_t L,
+                                                        uint64_t batch, uint32_t depth, hipStream_t stream);
 
 /*
  * Tile table of the LDS-resident 32-bit path (paper Sec. 2.6, matrix dimension

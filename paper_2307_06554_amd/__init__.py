@@ -19,6 +19,7 @@ from .binding import (  # noqa: F401
     polymul_negacyclic_rns,
     polymul_negacyclic_rns_crt,
     polymul_negacyclic_rns_karatsuba,
+    polymul_negacyclic_rns_karatsuba_noalloc,
     polymul_negacyclic_rns_shared,
     polymul_negacyclic_shared,
     polymul_negacyclic_u64_shared,

@@ -14,7 +14,8 @@ _LIB_NAME = "libpolymul.so"
 _lib = None
 
 STATUS = {0: "POLYMUL_OK", 1: "POLYMUL_EINVAL", 2: "POLYMUL_EALIAS", 3: "POLYMUL_EUNSUPPORTED",
-          4: "POLYMUL_ENOMEM", 5: "POLYMUL_EDEVICE"}
+          4: "POLYMUL_ENOMEM", 5: "POLYMUL_EDEVICE", 6: "POLYMUL_ESCRATCH"}
+POLYMUL_NOALLOC_SCRATCH_BYTES = 64 << 20
 POLYMUL_PLAN_NO_GRAPH = 1
 
 # name -> (restype, argtypes) exactly as declared in include/polymul.h
@@ -43,6 +44,7 @@ _SIGNATURES = {
     "polymul_negacyclic_rns_karatsuba": (ctypes.c_int, [_vp, _vp, _vp, _u64, _vp, _u32, _u64, _u32, _vp, _u64,
                                                         _vp]),
     "polymul_tune_get": (ctypes.c_int, [_u64, _u32, ctypes.POINTER(_u32)]),
+    "polymul_negacyclic_rns_karatsuba_noalloc": (ctypes.c_int, [_vp, _vp, _vp, _u64, _vp, _u32, _u64, _u32, _vp]),
 }
 
 
@@ -284,6 +286,19 @@ def polymul_negacyclic_rns_karatsuba(a, b, qs, depth, workspace=None, out=None, 
         _words(a, 4, "a"), _words(b, 4, "b"), _words(c, 4, "out"), n, ctypes.cast(qarr, ctypes.c_void_p), L,
         batch, int(depth), ctypes.c_void_p(workspace.data_ptr()), ws_bytes, _stream(stream))
     _check(st, "polymul_negacyclic_rns_karatsuba")
+    return c
+
+
+def polymul_negacyclic_rns_karatsuba_noalloc(a, b, qs, depth, out=None, stream=None):
+    """polymul_negacyclic_rns_karatsuba with the library's own per-GPU scratch as the
+    workspace (no allocation in the call; calls on one GPU must not overlap)."""
+    batch, L, n = _rns_shape(a, b, qs)
+    c = _result(out, a, 4)
+    qarr = (ctypes.c_uint32 * L)(*[int(x) for x in qs])
+    st = load_library().polymul_negacyclic_rns_karatsuba_noalloc(
+        _words(a, 4, "a"), _words(b, 4, "b"), _words(c, 4, "out"), n, ctypes.cast(qarr, ctypes.c_void_p), L,
+        batch, int(depth), _stream(stream))
+    _check(st, "polymul_negacyclic_rns_karatsuba_noalloc")
     return c
 
 

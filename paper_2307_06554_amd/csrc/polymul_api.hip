@@ -516,6 +516,78 @@ polymul_status kara_workspace(uint64_t n, uint64_t products, uint32_t depth, uin
   return POLYMUL_OK;
 }
 
+// The RNS Karatsuba route on validated arguments with a workspace of at least
+// kara_workspace(n, batch * L, depth, 4) bytes: split, sub-products, combine.
+polymul_status run_rns_karatsuba(const uint32_t* a, const uint32_t* b, uint32_t* c, uint64_t n, const uint32_t* q,
+                                 uint32_t L, uint64_t batch, uint32_t depth, void* workspace, hipStream_t stream) {
+  const uint32_t nsub = depth == 1 ? 3 : depth == 2 ? 9 : 27;
+  const uint32_t np = (uint32_t)(n >> depth);
+  const uint64_t nprod = batch * L;
+  const uint64_t sub_words = nprod * nsub * np;
+  KaraParams K{};
+  K.a = a; K.b = b; K.c = c;
+  K.sa = (uint32_t*)workspace;
+  K.sb = K.sa + sub_words;
+  uint32_t* sc = K.sb + sub_words;
+  K.sc = sc;
+  K.nprod = nprod; K.n = (uint32_t)n; K.np = np; K.depth = depth; K.nsub = nsub; K.L = L;
+  const int Lq = limbs32(q, L);
+  for (uint32_t l = 0; l < L; ++l) K.mods[l] = make_mod32(q[l], Lq);
+  const uint64_t threads = nprod * np;
+  const uint64_t blocks = (threads + 255) / 256;
+  if (blocks > 0x7FFFFFFFull) return POLYMUL_EUNSUPPORTED;
+  polymul_status st = kara_split(K, depth, blocks, stream);
+  if (st != POLYMUL_OK) return st;
+  // the sub-products: nprod * nsub products of degree bound n' with modulus (i / nsub) % L
+  st = run_mfma32(K.sa, K.sb, sc, np, q, L, L, 0, nprod * nsub, stream, false, nsub);
+  if (st != POLYMUL_OK) return st;
+  return kara_combine(K, depth, blocks, stream);
+}
+
+// Validation shared by both RNS Karatsuba entry points; *need gets the workspace bytes.
+polymul_status check_rns_karatsuba(const uint32_t* a, const uint32_t* b, const uint32_t* c, uint64_t n,
+                                   const uint32_t* q, uint32_t L, uint64_t batch, uint32_t depth, uint64_t* need,
+                                   uint64_t* bytes) {
+  if (L == 0 || L > 16 || !q) return POLYMUL_EINVAL;
+  for (uint32_t l = 0; l < L; ++l)
+    if (q[l] < 2) return POLYMUL_EINVAL;
+  polymul_status st = kara_workspace(n, batch * L, depth, 4, need);
+  if (st != POLYMUL_OK) return st;
+  return check_arrays(a, b, c, n, batch, L, 4, bytes);
+}
+
+}  // namespace
+
+// Scratch of the allocation-free Karatsuba entry point: one copy on every GPU the
+// library runs on, set aside when the library's code is loaded there and kept
+// until the process ends.  In host code `scratch` names a host-side stand-in,
+// never the device memory: the device address comes from hipGetSymbolAddress.
+static __device__ __align__(256) uint8_t scratch[POLYMUL_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices];  // device address of `scratch`, per device (null: not looked up yet)
+
+// Device address of the current device's scratch, looked up once per device.
+polymul_status scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return POLYMUL_EUNSUPPORTED;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress");
+    if (!p) return POLYMUL_EDEVICE;
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return POLYMUL_OK;
+}
+
 // c = sum of the kparts runs' residues mod q, 64-bit words.
 __global__ __launch_bounds__(256) void split_sum64_kernel(const uint64_t* __restrict__ ws, uint64_t* __restrict__ c,
                                                           uint64_t words, uint32_t kparts, uint64_t q) {
@@ -628,6 +700,7 @@ const char* polymul_status_string(polymul_status s) {
     case POLYMUL_EUNSUPPORTED: return "POLYMUL_EUNSUPPORTED: not implemented for these arguments";
     case POLYMUL_ENOMEM: return "POLYMUL_ENOMEM: allocation failed";
     case POLYMUL_EDEVICE: return "POLYMUL_EDEVICE: HIP call or kernel launch failed";
+    case POLYMUL_ESCRATCH: return "POLYMUL_ESCRATCH: the call needs more scratch than the library holds";
   }
   return "POLYMUL_UNKNOWN_STATUS";
 }
@@ -1026,40 +1099,31 @@ polymul_status polymul_negacyclic_u64_karatsuba(const uint64_t* a, const uint64_
 polymul_status polymul_negacyclic_rns_karatsuba(const uint32_t* a, const uint32_t* b, uint32_t* c, uint64_t n,
                                                 const uint32_t* q, uint32_t L, uint64_t batch, uint32_t depth,
                                                 void* workspace, uint64_t workspace_bytes, hipStream_t stream) {
-  if (L == 0 || !q) return POLYMUL_EINVAL;
-  for (uint32_t l = 0; l < L; ++l)
-    if (q[l] < 2) return POLYMUL_EINVAL;
-  uint64_t need;
-  polymul_status st = polymul_karatsuba_workspace_size(n, L, batch, depth, &need);
-  if (st != POLYMUL_OK) return st;
-  uint64_t bytes;
-  st = check_arrays(a, b, c, n, batch, L, 4, &bytes);
+  uint64_t need, bytes;
+  polymul_status st = check_rns_karatsuba(a, b, c, n, q, L, batch, depth, &need, &bytes);
   if (st != POLYMUL_OK || batch == 0) return st;
   if (!workspace || ((uintptr_t)workspace & 15) || workspace_bytes < need) return POLYMUL_EINVAL;
   if (overlaps(workspace, need, a, bytes) || overlaps(workspace, need, b, bytes) || overlaps(workspace, need, c, bytes))
     return POLYMUL_EALIAS;
-  const uint32_t nsub = depth == 1 ? 3 : depth == 2 ? 9 : 27;
-  const uint32_t np = (uint32_t)(n >> depth);
-  const uint64_t nprod = batch * L;
-  const uint64_t sub_words = nprod * nsub * np;
-  KaraParams K{};
-  K.a = a; K.b = b; K.c = c;
-  K.sa = (uint32_t*)workspace;
-  K.sb = K.sa + sub_words;
-  uint32_t* sc = K.sb + sub_words;
-  K.sc = sc;
-  K.nprod = nprod; K.n = (uint32_t)n; K.np = np; K.depth = depth; K.nsub = nsub; K.L = L;
-  const int Lq = limbs32(q, L);
-  for (uint32_t l = 0; l < L; ++l) K.mods[l] = make_mod32(q[l], Lq);
-  const uint64_t threads = nprod * np;
-  const uint64_t blocks = (threads + 255) / 256;
-  if (blocks > 0x7FFFFFFFull) return POLYMUL_EUNSUPPORTED;
-  st = kara_split(K, depth, blocks, stream);
+  return run_rns_karatsuba(a, b, c, n, q, L, batch, depth, workspace, stream);
+}
+
+polymul_status polymul_negacyclic_rns_karatsuba_noalloc(const uint32_t* a, const uint32_t* b, uint32_t* c,
+                                                        uint64_t n, const uint32_t* q, uint32_t L, uint64_t batch,
+                                                        uint32_t depth, hipStream_t stream) {
+  uint64_t need, bytes;
+  polymul_status st = check_rns_karatsuba(a, b, c, n, q, L, batch, depth, &need, &bytes);
+  if (st != POLYMUL_OK || batch == 0) return st;
+  if (need > POLYMUL_NOALLOC_SCRATCH_BYTES) {
+    if (log_enabled())
+      fprintf(stderr, "polymul: the call needs %llu bytes of scratch, the library holds %llu\n",
+              (unsigned long long)need, (unsigned long long)POLYMUL_NOALLOC_SCRATCH_BYTES);
+    return POLYMUL_ESCRATCH;
+  }
+  void* ws = nullptr;
+  st = scratch_address(&ws);
   if (st != POLYMUL_OK) return st;
-  // the sub-products: nprod * nsub products of degree bound n' with modulus (i / nsub) % L
-  st = run_mfma32(K.sa, K.sb, sc, np, q, L, L, 0, nprod * nsub, stream, false, nsub);
-  if (st != POLYMUL_OK) return st;
-  return kara_combine(K, depth, blocks, stream);
+  return run_rns_karatsuba(a, b, c, n, q, L, batch, depth, ws, stream);
 }
 
 polymul_status polymul_tune_set(uint64_t n, uint32_t L, uint32_t t) {

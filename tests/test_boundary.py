@@ -177,6 +177,25 @@ def test_karatsuba_arguments():
     assert call(k, None, None, None, 256, qp, 2, 0, 2, None, 0, None) == 0     # empty batch
 
 
+def test_karatsuba_noalloc_arguments():
+    # the allocation-free route: the same argument checks, and a call needing more than
+    # the library's scratch is refused with POLYMUL_ESCRATCH, all before any HIP call
+    ESCRATCH = 6
+    qs = (ctypes.c_uint32 * 8)(*([1068236801] * 8))
+    qp = ctypes.cast(qs, ctypes.c_void_p)
+    k = "polymul_negacyclic_rns_karatsuba_noalloc"
+    assert pm.polymul_karatsuba_workspace_size(4096, 8, 256, 1) > binding.POLYMUL_NOALLOC_SCRATCH_BYTES
+    assert call(k, A, B, C, 4096, qp, 8, 256, 1, None) == ESCRATCH
+    assert call(k, A, B, C, 4096, qp, 8, 1, 0, None) == EINVAL        # depth 0
+    assert call(k, A, B, C, 4096, qp, 8, 1, 4, None) == EINVAL        # depth 4
+    assert call(k, A, B, C, 8, qp, 8, 1, 2, None) == EINVAL           # n / 2^depth < 4
+    assert call(k, A, B, C, 4096, None, 8, 1, 2, None) == EINVAL
+    assert call(k, A, B, C, 4096, qp, 0, 1, 2, None) == EINVAL
+    assert call(k, A, B, A + 64, 4096, qp, 8, 1, 2, None) == EALIAS   # c overlaps a
+    assert call(k, None, None, None, 4096, qp, 8, 0, 2, None) == 0    # empty batch
+    assert pm.polymul_status_string(ESCRATCH).startswith("POLYMUL_ESCRATCH")
+
+
 def test_shared_operand_arguments():
     qs = (ctypes.c_uint32 * 2)(17, 19)
     qp = ctypes.cast(qs, ctypes.c_void_p)
