@@ -67,47 +67,65 @@ inline ModQ32 make_mod32(uint32_t q, int L) {
   return m;
 }
 
+// High halves of products (device intrinsics; plain wide arithmetic on the host,
+// where these helpers are tested).
+__host__ __device__ __forceinline__ uint64_t mul_hi64(uint64_t a, uint64_t b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __umul64hi(a, b);
+#else
+  return (uint64_t)(((unsigned __int128)a * b) >> 64);
+#endif
+}
+__host__ __device__ __forceinline__ uint32_t mul_hi32(uint32_t a, uint32_t b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __umulhi(a, b);
+#else
+  return (uint32_t)(((uint64_t)a * b) >> 32);
+#endif
+}
+__host__ __device__ __forceinline__ uint32_t min_u32(uint32_t a, uint32_t b) { return a < b ? a : b; }
+
 // Barrett: x mod q for any 64-bit x, q < 2^32.  With mu = floor(2^64/q) >=
 // 2^64/q - 1 and x < 2^64, x*mu/2^64 > x/q - 1, so the quotient estimate is
 // floor(x/q) or one less and r = x - estimate*q lies in [0, 2q).
-__device__ __forceinline__ uint32_t reduce_u64(uint64_t x, const ModQ32& m) {
-  const uint64_t qe = __umul64hi(x, m.mu);
+__host__ __device__ __forceinline__ uint32_t reduce_u64(uint64_t x, const ModQ32& m) {
+  const uint64_t qe = mul_hi64(x, m.mu);
   uint64_t r = x - qe * (uint64_t)m.q;
   if (r >= m.q) r -= m.q;
   return (uint32_t)r;
 }
 // The same for q < 2^31: then r < 2q < 2^32, so r is the low word of
 // x - estimate*q and the tail is 32-bit arithmetic.
-__device__ __forceinline__ uint32_t reduce_u64_q31(uint64_t x, uint64_t mu, uint32_t q) {
-  const uint64_t qe = __umul64hi(x, mu);
+__host__ __device__ __forceinline__ uint32_t reduce_u64_q31(uint64_t x, uint64_t mu, uint32_t q) {
+  const uint64_t qe = mul_hi64(x, mu);
   const uint32_t r = (uint32_t)x - (uint32_t)qe * q;
-  return min(r, r - q);
+  return min_u32(r, r - q);
 }
 // x mod q for a 32-bit word.  With m32 = floor(2^32/q) >= 2^32/q - 1 and x < 2^32,
 // x*m32/2^32 > x/q - 1, so the estimate floor(x*m32/2^32) is floor(x/q) or one
 // less and r = x - estimate*q lies in [0, 2q) (and below 2^32: m32 = 1 when
 // q > 2^31).  One conditional subtraction ends it; min(r, r - q) is that
 // subtraction, r - q wrapping above r when r < q.
-__device__ __forceinline__ uint32_t reduce_u32(uint32_t x, const ModQ32& m) {
-  const uint32_t qe = __umulhi(x, m.m32);
+__host__ __device__ __forceinline__ uint32_t reduce_u32(uint32_t x, const ModQ32& m) {
+  const uint32_t qe = mul_hi32(x, m.m32);
   const uint32_t r = x - qe * m.q;
-  return min(r, r - m.q);
+  return min_u32(r, r - m.q);
 }
 // Signed |x| < 2^62 (x + lift is in (0, 2^63 + 2^32), added as unsigned words).
-__device__ __forceinline__ uint32_t reduce_i64(int64_t x, const ModQ32& m) {
+__host__ __device__ __forceinline__ uint32_t reduce_i64(int64_t x, const ModQ32& m) {
   return reduce_u64((uint64_t)x + m.lift, m);
 }
 
 // L digits of the residue x (already in [0, q)), packed little-endian in a word.
 template <int L>
-__device__ __forceinline__ uint32_t digits32(uint32_t x, uint32_t q, uint32_t thr) {
+__host__ __device__ __forceinline__ uint32_t digits32(uint32_t x, uint32_t q, uint32_t thr) {
   constexpr uint32_t B = (uint32_t)limb_bias(L);
   uint32_t v = x <= thr ? x : x - q;  // wraps mod 2^32: the representative in W_L
   return (v + B) ^ B;
 }
 // Digits of -x mod q.
 template <int L>
-__device__ __forceinline__ uint32_t neg_digits32(uint32_t x, uint32_t q, uint32_t thr) {
+__host__ __device__ __forceinline__ uint32_t neg_digits32(uint32_t x, uint32_t q, uint32_t thr) {
   return digits32<L>(x == 0 ? 0u : q - x, q, thr);
 }
 // Both digit words of residues x in [0, q): of x and of a representative of -x.
@@ -115,7 +133,7 @@ __device__ __forceinline__ uint32_t neg_digits32(uint32_t x, uint32_t q, uint32_
 // x and q - x are in the window as they are; q - 0 = q stands for 0.
 // Four residues at a time, the window test taken once.
 template <int L>
-__device__ __forceinline__ void digits_pm32(const uint32_t (&x)[4], uint32_t q, uint32_t thr, uint32_t (&pos)[4],
+__host__ __device__ __forceinline__ void digits_pm32(const uint32_t (&x)[4], uint32_t q, uint32_t thr, uint32_t (&pos)[4],
                                             uint32_t (&neg)[4]) {
   constexpr uint32_t B = (uint32_t)limb_bias(L);
   if (q <= thr) {
