@@ -12,7 +12,6 @@ CRT (polymul_negacyclic_rns_crt), all reported beside the headline, and the
 plain integer kernel.  --all also times the other workloads (to stderr).
 """
 import argparse
-import hashlib
 import json
 import os
 import platform
@@ -28,15 +27,6 @@ WORKLOAD_INDEX = 2
 KERNEL = "mfma32_group_kernel<4,false>"
 
 
-def csrc_hash():
-    h = hashlib.sha256()
-    d = os.path.join(ROOT, "paper_2307_06554_amd", "csrc")
-    for name in sorted(os.listdir(d)):
-        with open(os.path.join(d, name), "rb") as f:
-            h.update(name.encode() + f.read())
-    return h.hexdigest()[:16]
-
-
 def measured_traffic():
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
     --pmc summary, only if it was taken on the current kernel sources."""
@@ -46,6 +36,7 @@ def measured_traffic():
             rec = json.load(f)
     except (OSError, ValueError):
         return None
+    from paper_2307_06554_amd.tune import csrc_hash
     if rec.get("csrc_hash") != csrc_hash():
         return None
     return rec.get("hbm_bytes_per_launch")
@@ -60,6 +51,7 @@ def measured_mfma_busy():
             rec = json.load(f)
     except (OSError, ValueError):
         return None
+    from paper_2307_06554_amd.tune import csrc_hash
     if rec.get("csrc_hash") != csrc_hash():
         return None
     return rec.get("mfma_busy")
@@ -188,12 +180,15 @@ def other_workloads(steps, warmup):
     c = torch.empty_like(a)
     ms = time_steps(lambda: pm.polymul_negacyclic_u64(a, b, w.q, out=c), max(2, steps // 20), 2)
     ops = 2 * 64 * w.n * w.n * a.shape[0]
-    ws = torch.empty(pm.polymul_karatsuba_u64_workspace_size(w.n, a.shape[0], 3), dtype=torch.uint8, device=dev)
+    dk = pm.polymul_tune_get_karatsuba(w.n, a.shape[0], 8)
+    ws = torch.empty(max(16, pm.polymul_karatsuba_u64_workspace_size(w.n, a.shape[0], dk)), dtype=torch.uint8,
+                     device=dev)
     ck = torch.empty_like(a)
-    msk = time_steps(lambda: pm.polymul_negacyclic_u64_karatsuba(a, b, w.q, 3, workspace=ws, out=ck),
+    msk = time_steps(lambda: pm.polymul_negacyclic_u64_karatsuba(a, b, w.q, dk, workspace=ws, out=ck),
                      max(2, steps // 20), 2)
     out[w.name] = {"polymuls_per_s": a.shape[0] / ms * 1e3, "ms_per_step": ms, "int8_tops": ops / ms / 1e9,
-                   "karatsuba_depth3_polymuls_per_s": a.shape[0] / msk * 1e3, "karatsuba_ms_per_step": msk,
+                   "karatsuba_depth": dk, "karatsuba_polymuls_per_s": a.shape[0] / msk * 1e3,
+                   "karatsuba_ms_per_step": msk,
                    "karatsuba_bit_identical": bool(torch.equal(c, ck))}
     return out
 
@@ -210,7 +205,8 @@ def main():
                     help="untimed seconds of the headline launch before its warm-up steps (clock settling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--all", action="store_true", help="also time the other workloads (stderr)")
-    ap.add_argument("--karatsuba-depth", type=int, default=2, help="0 skips the Karatsuba route")
+    ap.add_argument("--karatsuba-depth", type=int, default=0,
+                    help="levels of the Karatsuba route (0: the tuned depth; -1 skips the route)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first copy this many MiB device-to-device (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -260,9 +256,9 @@ def main():
     plain_value = products / (ms_plain / 1e3)
 
     kara = None
-    if args.karatsuba_depth:
-        d = args.karatsuba_depth
-        ws = torch.empty(pm.polymul_karatsuba_workspace_size(n, L, B, d), dtype=torch.uint8, device=dev)
+    if args.karatsuba_depth >= 0:
+        d = args.karatsuba_depth or pm.polymul_tune_get_karatsuba(n, products, 4)
+        ws = torch.empty(max(16, pm.polymul_karatsuba_workspace_size(n, L, B, d)), dtype=torch.uint8, device=dev)
         ck = torch.empty_like(a)
         ms_k = time_steps(lambda: pm.polymul_negacyclic_rns_karatsuba(a, b, w.qs, d, workspace=ws, out=ck),
                           args.steps, args.warmup)
@@ -271,7 +267,8 @@ def main():
         sub_ops = 2 * 16 * (n >> d) ** 2 * 3 ** d * products
         kara = {"depth": d, "value": products / (ms_k / 1e3), "unit": "polymuls/s", "ms_per_step": ms_k,
                 "speedup_vs_direct": ms / ms_k, "bit_identical_to_direct": bool(torch.equal(ck, c)),
-                "kernels": "split, mfma32_group_kernel on 3^d sub-products of degree n/2^d, combine",
+                "kernels": ("split, matrix kernel on 3^d sub-products of degree n/2^d, combine" if d else
+                            "direct route (the tuned depth is 0)"),
                 "mfma_ops_per_step": sub_ops, "schoolbook_equivalent_tops": 2 * 16 * n * n * products / ms_k / 1e9}
         del ws, ck
 

@@ -198,7 +198,11 @@ polymul_status polymul_negacyclic_u64_shared(const uint64_t* a, const uint64_t* 
  *
  *   a, b, c, n, q, L, batch: as for polymul_negacyclic_rns (L <= 16; L <= 8
  *                when n / 2^depth > 8192).
- *   depth:       1, 2 or 3, with n / 2^depth >= 4.
+ *   depth:       1, 2 or 3, with n / 2^depth >= 4; or 0 for the tuned choice
+ *                for this degree bound and number of products (batch * L):
+ *                polymul_tune_set_karatsuba, else a built-in one.  Where that
+ *                choice is the direct route (no levels) the call is
+ *                polymul_negacyclic_rns and the workspace is not used.
  *   workspace:   device, 16-byte aligned, at least
  *                polymul_karatsuba_workspace_size(...) bytes, owned by the
  *                caller, not overlapping a, b or c; its contents on entry do
@@ -213,8 +217,9 @@ polymul_status polymul_karatsuba_workspace_size(uint64_t n, uint32_t L, uint64_t
 /*
  * The same route for 64-bit words and one modulus q < 2^64 (a, b, c as for
  * polymul_negacyclic_u64): the sub-products run on the K-streaming kernel,
- * their K range cut into up to four runs when that fills the GPU's rounds of
- * workgroups better.  Workspace rules and errors as above, sized by
+ * their K range cut into up to four runs (POLYMUL_TUNE_U64_KARATSUBA_RUNS) when
+ * that fills the GPU's rounds of workgroups better.  depth 0 takes the tuned
+ * choice for (n, batch) as above, the direct polymul_negacyclic_u64 included.  Workspace rules and errors as above, sized by
  * polymul_karatsuba_u64_workspace_size (room for the runs included).
  */
 polymul_status polymul_karatsuba_u64_workspace_size(uint64_t n, uint64_t batch, uint32_t depth,
@@ -254,7 +259,9 @@ polymul_status polymul_negacyclic_rns_karatsuba_noalloc(const uint32_t* a, const
  * selection: the best block size is found by experiment).  For degree bound n
  * and limb count L (1..4), t is the side of the Toeplitz tiles the product is
  * cut into (n = t * r): n itself when n <= 32, otherwise a power of two in
- * [32, min(n, 128)].  t = 0 restores the built-in choice.  The table is
+ * [32, min(n, 128)] (32x32 output tiles, v_mfma_i32_32x32x32_i8), or 16 for
+ * 64 <= n <= 512 (16x16 output tiles, v_mfma_i32_16x16x64_i8, the built-in
+ * choice there).  t = 0 restores the built-in choice.  The table is
  * process-wide; the autotuner (paper_2307_06554_amd/tune.py) times the
  * candidates on the GPU and calls polymul_tune_set with the winners.  Takes
  * effect for launches and plans created afterwards.  No HIP call is made.
@@ -262,6 +269,37 @@ polymul_status polymul_negacyclic_rns_karatsuba_noalloc(const uint32_t* a, const
  */
 polymul_status polymul_tune_set(uint64_t n, uint32_t L, uint32_t t);
 polymul_status polymul_tune_get(uint64_t n, uint32_t L, uint32_t* t);
+
+/*
+ * Process-wide scheduling knobs of grouped plans (paper Sec. 2.6: parameters
+ * found by experiment), read when a plan is created; results never depend on
+ * them.  No HIP call is made.  EINVAL: unknown parameter or value out of range.
+ *   POLYMUL_TUNE_PLAN_SHARE_PCT (10..1000, default 100): items estimated to take
+ *     longer than this percentage of a CU's even share of the plan's work have
+ *     their K range cut into runs.
+ *   POLYMUL_TUNE_PLAN_STREAM_PCT (50..400, default 125): weight of a K-streamed
+ *     block's matrix work against a resident group's in those estimates.
+ *   POLYMUL_TUNE_U64_KARATSUBA_RUNS (1, 2 or 4, default 4): most K runs the
+ *     64-bit Karatsuba route cuts its streamed sub-products into.
+ */
+#define POLYMUL_TUNE_PLAN_SHARE_PCT 1u
+#define POLYMUL_TUNE_PLAN_STREAM_PCT 2u
+#define POLYMUL_TUNE_U64_KARATSUBA_RUNS 3u
+polymul_status polymul_tune_param_set(uint32_t param, uint64_t value);
+polymul_status polymul_tune_param_get(uint32_t param, uint64_t* value);
+
+/*
+ * Karatsuba depth table (paper Sec. 4, Karatsuba; Sec. 2.6, parameters by
+ * experiment): the depth that depth 0 resolves to for degree bound n and calls
+ * of `products` products (batch * L for the RNS route, batch for the 64-bit
+ * route; bucketed by floor(log2 products)), for 32-bit (elem_bytes 4) or 64-bit
+ * (8) words.  depth 0 = the direct route, 1..3 = levels, 0xFF = back to the
+ * built-in choice.  The get call returns the depth in force.  No HIP call.
+ * EINVAL: bad n, products, elem_bytes or depth.
+ */
+polymul_status polymul_tune_set_karatsuba(uint64_t n, uint64_t products, uint32_t elem_bytes, uint32_t depth);
+polymul_status polymul_tune_get_karatsuba(uint64_t n, uint64_t products, uint32_t elem_bytes, uint32_t* depth);
+
 
 #ifdef __cplusplus
 }

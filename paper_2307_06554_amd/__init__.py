@@ -31,5 +31,9 @@ from .binding import (  # noqa: F401
     polymul_status_string,
     polymul_tune_get,
     polymul_tune_set,
+    polymul_tune_get_karatsuba,
+    polymul_tune_set_karatsuba,
+    polymul_tune_param_get,
+    polymul_tune_param_set,
     Plan,
 )

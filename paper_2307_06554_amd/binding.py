@@ -45,7 +45,13 @@ _SIGNATURES = {
                                                         _vp]),
     "polymul_tune_get": (ctypes.c_int, [_u64, _u32, ctypes.POINTER(_u32)]),
     "polymul_negacyclic_rns_karatsuba_noalloc": (ctypes.c_int, [_vp, _vp, _vp, _u64, _vp, _u32, _u64, _u32, _vp]),
+    "polymul_tune_param_set": (ctypes.c_int, [_u32, _u64]),
+    "polymul_tune_param_get": (ctypes.c_int, [_u32, ctypes.POINTER(_u64)]),
+    "polymul_tune_set_karatsuba": (ctypes.c_int, [_u64, _u64, _u32, _u32]),
+    "polymul_tune_get_karatsuba": (ctypes.c_int, [_u64, _u64, _u32, ctypes.POINTER(_u32)]),
 }
+TUNE_PARAMS = {"plan_share_pct": 1, "plan_stream_pct": 2, "u64_karatsuba_runs": 3}
+KARATSUBA_BUILTIN = 0xFF
 
 
 class PolymulError(RuntimeError):
@@ -68,6 +74,9 @@ def load_library():
     global _lib
     if _lib is not None:
         return _lib
+    # torch first: its HIP runtime must be the one the library binds to, so that
+    # the library's launches and torch's memory and streams share one runtime
+    import torch  # noqa: F401
     path = lib_path()
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build the HIP library first (__graft_entry__.build())")
@@ -280,7 +289,7 @@ def polymul_negacyclic_rns_karatsuba(a, b, qs, depth, workspace=None, out=None, 
     need = polymul_karatsuba_workspace_size(n, L, batch, depth)
     if workspace is None:
         workspace = torch.empty(max(need, 16), dtype=torch.uint8, device=a.device)
-    ws_bytes = workspace.numel() * workspace.element_size()
+    ws_bytes = workspace.numel() * workspace.element_size()  # depth 0 may need none
     qarr = (ctypes.c_uint32 * L)(*[int(x) for x in qs])
     st = load_library().polymul_negacyclic_rns_karatsuba(
         _words(a, 4, "a"), _words(b, 4, "b"), _words(c, 4, "out"), n, ctypes.cast(qarr, ctypes.c_void_p), L,
@@ -360,6 +369,30 @@ def polymul_plan_destroy(plan):
 def polymul_tune_set(n, L, t):
     """Set the Toeplitz tile side of the resident 32-bit path for (n, L); 0 = built-in."""
     _check(load_library().polymul_tune_set(int(n), int(L), int(t)), "polymul_tune_set")
+
+
+def polymul_tune_param_set(name, value):
+    """Set a plan scheduling knob by name (see TUNE_PARAMS)."""
+    _check(load_library().polymul_tune_param_set(TUNE_PARAMS[name], int(value)), "polymul_tune_param_set")
+
+
+def polymul_tune_param_get(name):
+    out = ctypes.c_uint64()
+    _check(load_library().polymul_tune_param_get(TUNE_PARAMS[name], ctypes.byref(out)), "polymul_tune_param_get")
+    return out.value
+
+
+def polymul_tune_set_karatsuba(n, products, elem_bytes, depth):
+    """Karatsuba depth that depth 0 resolves to for (n, products) and word size; 0xFF = built-in."""
+    _check(load_library().polymul_tune_set_karatsuba(int(n), int(products), int(elem_bytes), int(depth)),
+           "polymul_tune_set_karatsuba")
+
+
+def polymul_tune_get_karatsuba(n, products, elem_bytes):
+    out = ctypes.c_uint32()
+    _check(load_library().polymul_tune_get_karatsuba(int(n), int(products), int(elem_bytes), ctypes.byref(out)),
+           "polymul_tune_get_karatsuba")
+    return out.value
 
 
 def polymul_tune_get(n, L):

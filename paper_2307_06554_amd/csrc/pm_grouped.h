@@ -2,46 +2,83 @@
 //
 // Work items come from a device table sorted by decreasing cost (largest first)
 // and are claimed with one atomic add per item (a dynamic list schedule, which
-// with that order approximates longest-processing-time-first).  Each item is a
-// group of four 32x32 tiles of LDS-resident products (degrees 4..4096) or one
+// with that order approximates longest-processing-time-first).  Resident groups
+// run with as many int8 limbs as their modulus needs.  Each item is a
+// group of four 32x32 tiles of LDS-resident products (degrees 4..4096), a group
+// of products on 16x16 tiles (64..512, where the tile table says so) or one
 // 64x64 block of a K-streamed product (every other degree).  Algorithm 1's
 // GenConfig / ExtractDimensions run once on the host when the plan is built;
 // the launch only reads the resulting job table.
 #pragma once
 #include "pm_mfma32.h"
+#include "pm_mfma16.h"
 #include "pm_stream.h"
 
 namespace pm {
 
-enum : uint32_t { kJobResident = 0, kJobStream = 1 };
+enum : uint32_t { kJobResident = 0, kJobStream = 1, kJobSmall = 2 };
 
 struct GroupJob {
   uint32_t kind;
-  uint32_t pad[3];
-  Mfma32Params rp;   // kind == kJobResident
-  StreamParams sp;   // kind == kJobStream
+  uint32_t L;        // int8 limbs of a resident group: 2, 3 or 4 (from its modulus)
+  uint32_t pad[2];
+  Mfma32Params rp;   // kind == kJobResident, or kJobSmall (16x16 tiles, rp.slots products per item)
+  StreamParams sp;   // kind == kJobStream (4 limbs)
 };
 
 struct WorkItem {
   uint32_t group;    // index into the GroupJob table
-  uint32_t index;    // resident: tile-group index; stream: product * ublocks + u-block
+  uint32_t index;    // resident: tile-group index; small: group of rp.slots products;
+                     // stream: product * ublocks + u-block
 };
 
+template <int L>
+__device__ __forceinline__ void resident_item(const Mfma32Params& P, uint32_t index, uint8_t* smem) {
+  if (P.kparts > 1) resident_group_split<L>(P, index, smem);
+  else resident_group<L, false>(P, index, smem);
+}
+template <int L>
+__device__ __forceinline__ void small_item(const Mfma32Params& P, uint32_t index, uint8_t* smem) {
+  small_group<L>(P, index, smem, (Slot16*)(smem + P.slots * P.slot_bytes));
+}
+
+// Workgroup b starts with item b (the grid is no larger than the list), and every
+// later item comes from the queue, whose k-th claim is item grid + k.  The claim of
+// a workgroup's next item is issued when its current item starts and read when it
+// ends, so that the atomic's round trip overlaps the current item's work.
 // counter[0] is the queue, counter[1] counts the workgroups that have left; the last
 // to leave sets both back to zero, so that the next launch (a graph replay) starts
 // from an empty queue without a reset node.  Every workgroup's final claim has
 // returned before it counts itself out, so no claim can follow the reset.
-template <int L>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void grouped_kernel(const GroupJob* __restrict__ jobs, const WorkItem* __restrict__ items, uint32_t nitems,
                     uint32_t* counter) {
   extern __shared__ __align__(16) uint8_t smem[];
-  __shared__ uint32_t claimed;
+  __shared__ uint32_t next_item;
+  uint32_t it = blockIdx.x;
   for (;;) {
-    if (threadIdx.x == 0) claimed = atomicAdd(counter, 1u);
-    __syncthreads();
-    const uint32_t it = claimed;
-    __syncthreads();  // every wave has read `claimed` before it is written again
+    uint32_t claim = 0;
+    if (threadIdx.x == 0) claim = atomicAdd(counter, 1u) + gridDim.x;  // waited for at the end of the item
+    const WorkItem w = items[it];
+    const GroupJob& job = jobs[w.group];
+    if (job.kind == kJobResident) {
+      switch (job.L) {
+        case 2: resident_item<2>(job.rp, w.index, smem); break;
+        case 3: resident_item<3>(job.rp, w.index, smem); break;
+        default: resident_item<4>(job.rp, w.index, smem); break;
+      }
+    } else if (job.kind == kJobSmall) {
+      switch (job.L) {
+        case 2: small_item<2>(job.rp, w.index, smem); break;
+        case 3: small_item<3>(job.rp, w.index, smem); break;
+        default: small_item<4>(job.rp, w.index, smem); break;
+      }
+    } else {
+      stream_block<4, uint32_t>(job.sp, w.index, smem);
+    }
+    if (threadIdx.x == 0) next_item = claim;
+    __syncthreads();  // LDS is reused by the next item; next_item is visible
+    it = next_item;
     if (it >= nitems) {  // uniform: every wave leaves together
       if (threadIdx.x == 0 && atomicAdd(counter + 1, 1u) == gridDim.x - 1) {
         atomicExch(counter, 0u);
@@ -49,14 +86,7 @@ void grouped_kernel(const GroupJob* __restrict__ jobs, const WorkItem* __restric
       }
       break;
     }
-    const WorkItem w = items[it];
-    const GroupJob& job = jobs[w.group];
-    if (job.kind == kJobResident) {
-      if (job.rp.kparts > 1) resident_group_split<L>(job.rp, w.index, smem);
-      else resident_group<L, false>(job.rp, w.index, smem);
-    }
-    else stream_block<L, uint32_t>(job.sp, w.index, smem);
-    __syncthreads();  // LDS is reused by the next item
+    __syncthreads();  // every wave has read next_item before it is written again
   }
 }
 

@@ -518,62 +518,113 @@ __device__ __forceinline__ void stage_zero_fill(const Mfma32Params& P, const Gro
 // operand (n/4 >= 64), so wave w takes runs w, w + 4, ... and slot, operand and
 // modulus are uniform over the wave; lane l handles item 64 run + l.  The slots'
 // operand offsets and modulus constants sit in lanes 0..3 and are picked with
-// v_readlane, so the per-run selection has no branches.
-template <int L>
-__device__ __forceinline__ void stage_runs(const Mfma32Params& P, const GroupInfo& gi, uint8_t* smem) {
+// v_readlane, so the per-run selection has no branches.  A pass covers the
+// wave's next kPrefetch runs: its loads are issued first (runs_issue), then
+// converted into LDS (runs_convert).
+struct RunConsts {
+  uint32_t lao, lao_hi, lbo, lbo_hi;  // lane s < 4: word offsets of slot s's a and b
+  uint32_t lq, lthr, lm32;            // lane s < 4: slot s's modulus constants
+};
+
+__device__ __forceinline__ RunConsts run_consts(const Mfma32Params& P, const GroupInfo& gi) {
+  RunConsts rc;
+  uint64_t ao[4], bo[4];
+  uint32_t mq[4], mthr[4], mm32[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    ao[s] = gi.gp[s] * P.n;
+    bo[s] = b_product(P, gi.gp[s], gi.li[s]) * P.n;
+    const ModQ32& m = P.mods[gi.li[s]];
+    mq[s] = m.q;
+    mthr[s] = m.thr;
+    mm32[s] = m.m32;
+  }
+  const uint32_t ls = threadIdx.x & 3;
+  const uint64_t a64 = sel4(ao, ls), b64 = sel4(bo, ls);
+  rc.lao = (uint32_t)a64; rc.lao_hi = (uint32_t)(a64 >> 32);
+  rc.lbo = (uint32_t)b64; rc.lbo_hi = (uint32_t)(b64 >> 32);
+  rc.lq = sel4(mq, ls); rc.lthr = sel4(mthr, ls); rc.lm32 = sel4(mm32, ls);
+  return rc;
+}
+
+__device__ __forceinline__ uint32_t pick_lane(uint32_t v, uint32_t s) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)s);
+}
+
+// Loads of the pass starting at run r0 (r0 = wave + 4 kPrefetch * pass).  Every
+// load is issued (a run past the wave's last re-reads the last one), so that the
+// conversion can start on the first run while the rest are in flight.
+__device__ __forceinline__ void runs_issue(const Mfma32Params& P, const GroupInfo& gi, const RunConsts& rc,
+                                           uint32_t r0, uint4 (&pf)[kPrefetch]) {
   const uint32_t log2rps = P.log2n - 7, a_runs = P.n >> 8;  // runs per slot (n/2) / 64, of them a's (n/4) / 64
   const uint32_t nruns = gi.nslots << log2rps, rmask = (1u << log2rps) - 1;
   const uint32_t lane = threadIdx.x & 63, wave = wave_uniform(threadIdx.x >> 6);
-  uint32_t lao, lao_hi, lbo, lbo_hi, lq, lthr, lm32;
-  {
-    uint64_t ao[4], bo[4];
-    uint32_t mq[4], mthr[4], mm32[4];
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      ao[s] = gi.gp[s] * P.n;
-      bo[s] = b_product(P, gi.gp[s], gi.li[s]) * P.n;
-      const ModQ32& m = P.mods[gi.li[s]];
-      mq[s] = m.q;
-      mthr[s] = m.thr;
-      mm32[s] = m.m32;
-    }
-    const uint32_t ls = lane & 3;
-    const uint64_t a64 = sel4(ao, ls), b64 = sel4(bo, ls);
-    lao = (uint32_t)a64; lao_hi = (uint32_t)(a64 >> 32);
-    lbo = (uint32_t)b64; lbo_hi = (uint32_t)(b64 >> 32);
-    lq = sel4(mq, ls); lthr = sel4(mthr, ls); lm32 = sel4(mm32, ls);
-  }
-  auto pick = [](uint32_t v, uint32_t s) { return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)s); };
   if (wave >= nruns) return;
   const uint32_t last = wave + 4 * ((nruns - 1 - wave) >> 2);  // this wave's last run
-  for (uint32_t r0 = wave; r0 < nruns; r0 += 4 * kPrefetch) {
-    // every load is issued (a run past this wave's last re-reads the last one),
-    // so the conversion below can start on the first run while the rest are in flight
-    uint4 pf[kPrefetch];
 #pragma unroll
-    for (int k = 0; k < kPrefetch; ++k) {
-      const uint32_t run = min(r0 + 4 * k, last);
+  for (int k = 0; k < kPrefetch; ++k) {
+    const uint32_t run = min(r0 + 4 * k, last);
+    const uint32_t sl = run >> log2rps, cr = run & rmask;
+    const uint32_t* src =
+        cr < a_runs ? P.a + (((uint64_t)pick_lane(rc.lao_hi, sl) << 32) | pick_lane(rc.lao, sl)) + cr * 256u
+                    : P.b + (((uint64_t)pick_lane(rc.lbo_hi, sl) << 32) | pick_lane(rc.lbo, sl)) + (cr - a_runs) * 256u;
+    pf[k] = ((const uint4*)src)[lane];
+  }
+}
+
+template <int L>
+__device__ __forceinline__ void runs_convert(const Mfma32Params& P, const GroupInfo& gi, const RunConsts& rc,
+                                             uint8_t* smem, uint32_t r0, const uint4 (&pf)[kPrefetch]) {
+  const uint32_t log2rps = P.log2n - 7, a_runs = P.n >> 8;
+  const uint32_t nruns = gi.nslots << log2rps, rmask = (1u << log2rps) - 1;
+  const uint32_t lane = threadIdx.x & 63;
+#pragma unroll
+  for (int k = 0; k < kPrefetch; ++k) {
+    const uint32_t run = r0 + 4 * k;
+    if (run < nruns) {
       const uint32_t sl = run >> log2rps, cr = run & rmask;
-      const uint32_t* src =
-          cr < a_runs ? P.a + (((uint64_t)pick(lao_hi, sl) << 32) | pick(lao, sl)) + cr * 256u
-                      : P.b + (((uint64_t)pick(lbo_hi, sl) << 32) | pick(lbo, sl)) + (cr - a_runs) * 256u;
-      pf[k] = ((const uint4*)src)[lane];
-    }
-#pragma unroll
-    for (int k = 0; k < kPrefetch; ++k) {
-      const uint32_t run = r0 + 4 * k;
-      if (run < nruns) {
-        const uint32_t sl = run >> log2rps, cr = run & rmask;
-        ModQ32 m{};
-        m.q = pick(lq, sl);
-        m.thr = pick(lthr, sl);
-        m.m32 = pick(lm32, sl);
-        uint8_t* slot = smem + sl * P.slot_bytes;
-        if (cr < a_runs) stage_a_item<L>(P, slot, cr * 64 + lane, pf[k], m);
-        else stage_b_item<L>(P, slot + L * P.a_plane, gi.v_lo, (cr - a_runs) * 64 + lane, pf[k], m);
-      }
+      ModQ32 m{};
+      m.q = pick_lane(rc.lq, sl);
+      m.thr = pick_lane(rc.lthr, sl);
+      m.m32 = pick_lane(rc.lm32, sl);
+      uint8_t* slot = smem + sl * P.slot_bytes;
+      if (cr < a_runs) stage_a_item<L>(P, slot, cr * 64 + lane, pf[k], m);
+      else stage_b_item<L>(P, slot + L * P.a_plane, gi.v_lo, (cr - a_runs) * 64 + lane, pf[k], m);
     }
   }
+}
+
+template <int L>
+__device__ __forceinline__ void stage_runs(const Mfma32Params& P, const GroupInfo& gi, uint8_t* smem) {
+  const uint32_t nruns = gi.nslots << (P.log2n - 7);
+  const uint32_t wave = wave_uniform(threadIdx.x >> 6);
+  const RunConsts rc = run_consts(P, gi);
+  for (uint32_t r0 = wave; r0 < nruns; r0 += 4 * kPrefetch) {
+    uint4 pf[kPrefetch];
+    runs_issue(P, gi, rc, r0, pf);
+    runs_convert<L>(P, gi, rc, smem, r0, pf);
+  }
+}
+
+// The compute half of a group (after its staging barrier): each wave runs its
+// tile's K loop, then the recombination, reduction and stores.
+template <int L>
+__device__ __forceinline__ void resident_compute(const Mfma32Params& P, uint64_t grp, const GroupInfo& gi,
+                                                 const uint8_t* smem) {
+  const uint64_t total_units = P.nprod << P.log2U;
+  const uint32_t U = 1u << P.log2U;
+  const uint64_t unit = grp * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (unit >= total_units) return;
+  const uint64_t prod = unit >> P.log2U;
+  const uint32_t tile = (uint32_t)(unit & (U - 1));
+  const int zt = (int)(tile % P.tz), ut = (int)(tile / P.tz);
+  const uint32_t sl = (uint32_t)(prod - gi.first);
+  const uint8_t* slot = smem + sl * P.slot_bytes;
+  v16i acc[2 * L - 1];
+  mfma32_tile<L>(P, slot, slot + L * P.a_plane, 32 * zt, 32 * ut, gi.v_lo, acc);
+  uint32_t li;
+  const uint64_t gprod = global_product(P, prod, &li);
+  mfma32_epilogue<L>(P, gprod, P.mods[li], P.rcent[li], 32 * zt, 32 * ut, acc);
 }
 
 // One group of four 32x32 tiles: stage the products it touches, then each wave
@@ -581,8 +632,6 @@ __device__ __forceinline__ void stage_runs(const Mfma32Params& P, const GroupInf
 // past its last LDS read only if the caller synchronises afterwards.
 template <int L, bool SMALL>
 __device__ __forceinline__ void resident_group(const Mfma32Params& P, uint64_t grp, uint8_t* smem) {
-  const uint64_t total_units = P.nprod << P.log2U;
-  const uint32_t U = 1u << P.log2U;
   const GroupInfo gi = group_info(P, grp);
   if constexpr (SMALL) {
     for (uint32_t s = 0; s < gi.nslots; ++s)
@@ -611,19 +660,7 @@ __device__ __forceinline__ void resident_group(const Mfma32Params& P, uint64_t g
     stage_zero_fill<L>(P, gi, smem);
   }
   __syncthreads();
-  const uint64_t unit = grp * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (unit >= total_units) return;
-  const uint64_t prod = unit >> P.log2U;
-  const uint32_t tile = (uint32_t)(unit & (U - 1));
-  const int zt = (int)(tile % P.tz), ut = (int)(tile / P.tz);
-  const uint32_t sl = (uint32_t)(prod - gi.first);
-  const uint8_t* slot = smem + sl * P.slot_bytes;
-  const int v_lo = gi.v_lo;
-  v16i acc[2 * L - 1];
-  mfma32_tile<L>(P, slot, slot + L * P.a_plane, 32 * zt, 32 * ut, v_lo, acc);
-  uint32_t li;
-  const uint64_t gprod = global_product(P, prod, &li);
-  mfma32_epilogue<L>(P, gprod, P.mods[li], P.rcent[li], 32 * zt, 32 * ut, acc);
+  resident_compute<L>(P, grp, gi, smem);
 }
 
 // One run of a K-split group (one product, U >= 4: every wave has a tile):

@@ -11,6 +11,7 @@
 #include "../../include/polymul.h"
 #include "pm_common.h"
 #include "pm_mfma32.h"
+#include "pm_mfma16.h"
 #include "pm_plain.h"
 #include "pm_stream.h"
 #include "pm_grouped.h"
@@ -111,6 +112,7 @@ std::atomic<uint32_t> g_tile[17][5];
 
 uint32_t default_tile(uint32_t n) {
   if (n <= 32) return n;
+  if (n <= 512) return 16;  // the 16x16-tile kernel
   if (n <= 1024) return 32;
   return 64;
 }
@@ -120,8 +122,50 @@ uint32_t tile_for(uint32_t n, int L) {
   return t ? t : default_tile(n);
 }
 
+// Karatsuba depth per (log2 n, log2 of the products in the call): 0 = direct route,
+// 1..3 = levels; 0xFF = not tuned (the built-in choice).
+std::atomic<uint32_t> g_kara_depth[17][41];
+std::atomic<uint32_t> g_kara64_depth[17][41];
+constexpr uint32_t kNotTuned = 0xFF;
+struct KaraTableInit {
+  KaraTableInit() {
+    for (auto& row : g_kara_depth)
+      for (auto& v : row) v.store(kNotTuned);
+    for (auto& row : g_kara64_depth)
+      for (auto& v : row) v.store(kNotTuned);
+  }
+} g_kara_table_init;
+
+int ilog2_floor(uint64_t x) {
+  int l = 0;
+  while (l < 40 && (2ull << l) <= x) ++l;
+  return l;
+}
+
+// Depth for a call of `products` products of degree bound n: the table's, else the
+// built-in choice (two levels from n = 1024 on, one at 512 for 32-bit words; for
+// 64-bit words three from n = 8192 on, else one), never below n / 2^depth = 4.
+uint32_t kara_depth_for(uint64_t n, uint64_t products, bool wide) {
+  uint32_t d = (wide ? g_kara64_depth : g_kara_depth)[ilog2(n)][ilog2_floor(products)].load(std::memory_order_relaxed);
+  if (d == kNotTuned) d = wide ? (n >= 8192 ? 3 : 1) : (n >= 1024 ? 2 : n >= 512 ? 1 : 0);
+  while (d > 0 && (n >> d) < 4) --d;
+  return d;
+}
+
+// Grouped plans take the tuned side too (16: the 16x16-tile kernel).
+uint32_t plan_tile(uint32_t n, int L) { return tile_for(n, L); }
+
+// Products per item of a plan's 16x16-tile groups: up to 16, within half a CU's LDS.
+uint32_t plan_small_slots(uint32_t slot_bytes) {
+  uint32_t slots = kSlots16;
+  while (slots > 1 && (uint64_t)slots * slot_bytes + kSlots16 * sizeof(Slot16) > kMaxLds / 2) slots /= 2;
+  return slots;
+}
+
 // Valid tile sides for the resident path: n itself when n <= 32, else a power of two in [32, min(n, 128)].
+// t = 16 for 64 <= n <= 512 selects the 16x16-tile kernel (v_mfma_i32_16x16x64_i8).
 bool tile_ok(uint32_t n, uint32_t t) {
+  if (t == 16 && n >= 64 && n <= 512) return true;
   if (n <= 32) return t == n;
   return is_pow2(t) && t >= 32 && t <= 128 && t <= n;
 }
@@ -134,6 +178,25 @@ struct Geometry32 {
 // Degree split n = t * r (Sec. 2.5): t is the Toeplitz tile side.
 Geometry32 geometry32(uint32_t n, uint32_t t) {
   Geometry32 g{};
+  if (t == 16 && n >= 64) {
+    // 16x16 tiles: z < 16, u in tiles of 16, K-steps of 64 (four d values);
+    // reversed ext positions 0 .. n + 15 and the 5-dword over-read, B rows
+    // v in [-(r - 1), 16 tu - 1] of 16 bytes
+    g.t = 16;
+    g.r = n / 16;
+    g.spd = 1;
+    g.rowlen = 16;
+    g.tz = 1;
+    g.tu = (g.r + 15) / 16;
+    g.U = g.tu;
+    g.slots = kSlots16;
+    g.E = n - 1;
+    g.a_plane = (g.E + 24 + 15) & ~15u;
+    g.b_rows = 16 * g.tu + g.r - 1;
+    g.b_rowstride = 16;
+    g.b_plane = g.b_rows * 16;
+    return g;
+  }
   g.t = t;
   g.r = n / t;
   g.spd = g.t >= 32 ? g.t / 32 : 1;
@@ -215,8 +278,9 @@ polymul_status allow_lds() {
 }
 template <int L, bool SMALL> const void* k_group() { return (const void*)mfma32_group_kernel<L, SMALL>; }
 template <int L, typename W, int WPE> const void* k_stream() { return (const void*)stream_kernel<L, W, WPE>; }
-const void* k_grouped() { return (const void*)grouped_kernel<4>; }
+const void* k_grouped() { return (const void*)grouped_kernel; }
 template <int L> const void* k_shared() { return (const void*)mfma32_shared_kernel<L>; }
+template <int L> const void* k_small() { return (const void*)mfma16_group_kernel<L>; }
 
 template <int L, bool SMALL>
 polymul_status launch_mfma32_L(const Mfma32Params& P, uint32_t lds, hipStream_t s) {
@@ -224,6 +288,22 @@ polymul_status launch_mfma32_L(const Mfma32Params& P, uint32_t lds, hipStream_t 
   const uint64_t groups = ((P.nprod << P.log2U) + 3) / 4;
   if (groups > 0x7FFFFFFFull) return POLYMUL_EUNSUPPORTED;
   hipLaunchKernelGGL((mfma32_group_kernel<L, SMALL>), dim3((uint32_t)groups), dim3(kThreads), lds, s, P);
+  return launch_status();
+}
+
+// The 16x16-tile kernel: `slots` products per workgroup, as many as keep at least
+// two rounds of workgroups per CU (at least four, so that every wave has a tile).
+template <int L>
+polymul_status launch_small_L(Mfma32Params P, hipStream_t s) {
+  if (allow_lds<k_small<L>>() != POLYMUL_OK) return POLYMUL_EDEVICE;
+  uint32_t slots = kSlots16;
+  while (slots > 4 && (P.nprod + slots - 1) / slots < 2ull * device_cus()) slots /= 2;
+  while (slots > 1 && (uint64_t)slots * P.slot_bytes + kSlots16 * sizeof(Slot16) > kMaxLds / 2) slots /= 2;
+  P.slots = slots;
+  const uint64_t groups = (P.nprod + slots - 1) / slots;
+  if (groups > 0x7FFFFFFFull) return POLYMUL_EUNSUPPORTED;
+  const uint32_t lds = slots * P.slot_bytes + kSlots16 * (uint32_t)sizeof(Slot16);  // planes, then the slot table
+  hipLaunchKernelGGL((mfma16_group_kernel<L>), dim3((uint32_t)groups), dim3(kThreads), lds, s, P);
   return launch_status();
 }
 
@@ -471,6 +551,13 @@ polymul_status run_mfma32(const uint32_t* a, const uint32_t* b, uint32_t* c, uin
       fill_mfma32(P, a, b, c, n, qs, lc, nq_total, l0, nprod, L, tile_for(n, L), &lds, cyclic, lrep, b_shared);
   if (st != POLYMUL_OK) return st;
   const bool small = n < 4;
+  if (P.t == 16 && n >= 64) {
+    switch (L) {
+      case 2: return launch_small_L<2>(P, s);
+      case 3: return launch_small_L<3>(P, s);
+      default: return launch_small_L<4>(P, s);
+    }
+  }
   if (b_shared && !small && lrep == 1) return launch_shared(P, L, nprod / lc, s);
   switch (L) {
     case 2: return small ? launch_mfma32_L<2, true>(P, lds, s) : launch_mfma32_L<2, false>(P, lds, s);
@@ -499,15 +586,22 @@ polymul_status kara_combine(const KP& K, uint32_t depth, uint64_t blocks, hipStr
   return launch_status();
 }
 
-// Most K runs a streamed Karatsuba sub-product launch is cut into (whole rounds, see below).
+// Most K runs a streamed Karatsuba sub-product launch is cut into (whole rounds, see
+// below); polymul_tune_param_set can lower the cap.
 constexpr uint32_t kKaraRuns = 4;
+std::atomic<uint32_t> g_kara_runs_max{kKaraRuns};
 
 // Workspace bytes of one Karatsuba call: sub-operands of a and b and the sub-products
 // (3 words per sub-product coefficient), plus kKaraRuns copies of the sub-products for
 // runs when `runs` is set.
 polymul_status kara_workspace(uint64_t n, uint64_t products, uint32_t depth, uint32_t word, uint64_t* bytes,
                               bool runs = false) {
-  if (!bytes || depth < 1 || depth > 3 || !is_pow2(n) || n > 65536 || (n >> depth) < 4) return POLYMUL_EINVAL;
+  if (!bytes || !is_pow2(n) || n > 65536) return POLYMUL_EINVAL;
+  if (depth == 0) {  // the tuned depth; the direct route needs no workspace
+    depth = kara_depth_for(n, products, word == 8);
+    if (depth == 0) { *bytes = 0; return POLYMUL_OK; }
+  }
+  if (depth > 3 || (n >> depth) < 4) return POLYMUL_EINVAL;
   uint64_t nsub = 1;
   for (uint32_t l = 0; l < depth; ++l) nsub *= 3;
   const unsigned __int128 words = (unsigned __int128)products * nsub * (n >> depth);
@@ -548,7 +642,7 @@ polymul_status run_rns_karatsuba(const uint32_t* a, const uint32_t* b, uint32_t*
 polymul_status check_rns_karatsuba(const uint32_t* a, const uint32_t* b, const uint32_t* c, uint64_t n,
                                    const uint32_t* q, uint32_t L, uint64_t batch, uint32_t depth, uint64_t* need,
                                    uint64_t* bytes) {
-  if (L == 0 || L > 16 || !q) return POLYMUL_EINVAL;
+  if (L == 0 || L > 16 || !q || depth == 0) return POLYMUL_EINVAL;  // depth resolved by the caller
   for (uint32_t l = 0; l < L; ++l)
     if (q[l] < 2) return POLYMUL_EINVAL;
   polymul_status st = kara_workspace(n, batch * L, depth, 4, need);
@@ -633,7 +727,7 @@ polymul_status plan_attrs() {
 
 polymul_status plan_launch(const polymul_plan* p, hipStream_t s) {
   if (p->nitems) {
-    hipLaunchKernelGGL(grouped_kernel<4>, dim3(p->grid), dim3(kThreads), p->lds, s, p->d_jobs, p->d_items,
+    hipLaunchKernelGGL(grouped_kernel, dim3(p->grid), dim3(kThreads), p->lds, s, p->d_jobs, p->d_items,
                        p->nitems, p->d_counter);
     polymul_status st = launch_status();
     if (st != POLYMUL_OK) return st;
@@ -665,26 +759,44 @@ void plan_free(polymul_plan* p) {
   delete p;
 }
 
-// MFMA work of one item, for the largest-first order.
+// Plan scheduling knobs (polymul_tune_param_set): the split threshold as a percentage
+// of a CU's even share of the plan's work, and the weight of a streamed block's MFMA
+// work relative to a resident group's (its chunked staging and 128-bit flushes make
+// it slower than its MFMA count says), as a percentage.
+std::atomic<uint32_t> g_plan_share_pct{100};
+std::atomic<uint32_t> g_plan_stream_pct{125};
+
+// Estimated time of one item (MFMAs per wave of its four tiles, the streamed
+// blocks' weighted), for the largest-first order and the split decision.
 uint64_t item_cost(const GroupJob& j) {
+  if (j.kind == kJobSmall) {  // slots x tiles x K-steps of L^2 MFMAs of half the length
+    const uint64_t steps = j.rp.n >> 6;
+    return (uint64_t)j.rp.slots * (1u << j.rp.log2U) * steps * j.L * j.L / 2;
+  }
   if (j.kind == kJobResident) {
     const uint64_t steps = (uint64_t)j.rp.r << j.rp.log2spd;
-    return 4 * steps / j.rp.kparts;  // four tiles
+    return 4 * steps * j.L * j.L / j.rp.kparts;  // four tiles, L^2 MFMAs per K-step
   }
-  return (uint64_t)4 * ((uint64_t)j.sp.r << j.sp.log2spd) / j.sp.kparts;
+  const uint64_t steps = (uint64_t)j.sp.r << j.sp.log2spd;
+  return 4 * steps * 16 * g_plan_stream_pct.load(std::memory_order_relaxed) / 100 / j.sp.kparts;
 }
 
-// MFMA work of one unsplit item of a 32-bit group on its default route (resident for
+// The same for one unsplit item of a 32-bit group on its default route (resident for
 // n in [4, 4096], streamed otherwise), and the number of such items.
-void default_cost(uint32_t n, uint64_t count, uint64_t* items, uint64_t* cost) {
-  if (n >= 4 && n <= 4096) {
-    const Geometry32 g = geometry32(n, tile_for(n, 4));
+void default_cost(uint32_t n, uint64_t count, int L, uint64_t* items, uint64_t* cost) {
+  if (n >= 64 && plan_tile(n, L) == 16) {
+    const Geometry32 g = geometry32(n, 16);
+    const uint32_t slots = plan_small_slots((uint32_t)L * (g.a_plane + g.b_plane));
+    *items = (count + slots - 1) / slots;
+    *cost = (uint64_t)slots * g.U * (n >> 6) * L * L / 2;
+  } else if (n >= 4 && n <= 4096) {
+    const Geometry32 g = geometry32(n, plan_tile(n, L));
     *items = (count * g.U + 3) / 4;
-    *cost = 4 * (uint64_t)g.r * g.spd;
+    *cost = 4 * (uint64_t)g.r * g.spd * L * L;
   } else {
     const uint32_t t = n < 64 ? n : 64, r = n / t, spd = t >= 64 ? 2 : 1;
     *items = count * ((r + 63) / 64);
-    *cost = 4 * (uint64_t)r * spd;
+    *cost = 4 * (uint64_t)r * spd * 16 * g_plan_stream_pct.load(std::memory_order_relaxed) / 100;
   }
 }
 
@@ -783,11 +895,13 @@ polymul_status polymul_plan_create(polymul_plan** plan, const polymul_group* gro
   uint64_t total_cost = 0;
   for (uint32_t g = 0; g < ngroups; ++g) {
     if (groups[g].elem_bytes != 4 || groups[g].count == 0) continue;
+    const uint32_t q32 = (uint32_t)groups[g].q;
     uint64_t ni, ci;
-    default_cost((uint32_t)groups[g].n, groups[g].count, &ni, &ci);
+    default_cost((uint32_t)groups[g].n, groups[g].count, limbs32(&q32, 1), &ni, &ci);
     total_cost += ni * ci;
   }
-  const uint64_t share = std::max<uint64_t>(64, total_cost / device_cus());
+  const uint64_t share = std::max<uint64_t>(
+      64, total_cost / device_cus() * g_plan_share_pct.load(std::memory_order_relaxed) / 100);
   uint64_t part_words = 0;
   for (uint32_t g = 0; g < ngroups; ++g) {
     const polymul_group& G = groups[g];
@@ -809,12 +923,20 @@ polymul_status polymul_plan_create(polymul_plan** plan, const polymul_group* gro
     uint32_t lds = 0;
     polymul_status st;
     uint64_t ni, ci;
-    default_cost(n, G.count, &ni, &ci);
+    const int Lg = limbs32(&q32, 1);
+    default_cost(n, G.count, Lg, &ni, &ci);
     const bool split = ci > share;
-    if (n >= 4 && n <= 4096) {
+    job.L = (uint32_t)Lg;
+    if (n >= 64 && plan_tile(n, Lg) == 16) {
+      job.kind = kJobSmall;
+      st = fill_mfma32(job.rp, (const uint32_t*)G.a, (const uint32_t*)G.b, (uint32_t*)G.c, n, &q32, 1, 1, 0,
+                       G.count, Lg, 16, &lds);
+      job.rp.slots = plan_small_slots(job.rp.slot_bytes);
+      lds = job.rp.slots * job.rp.slot_bytes + kSlots16 * (uint32_t)sizeof(Slot16);
+    } else if (n >= 4 && n <= 4096) {
       job.kind = kJobResident;
       st = fill_mfma32(job.rp, (const uint32_t*)G.a, (const uint32_t*)G.b, (uint32_t*)G.c, n, &q32, 1, 1, 0,
-                       G.count, 4, tile_for(n, 4), &lds);
+                       G.count, Lg, plan_tile(n, Lg), &lds);
       if (st == POLYMUL_OK && split && job.rp.log2U >= 2) {  // groups of one product: every wave has a tile
         const uint32_t steps = job.rp.r << job.rp.log2spd;
         uint32_t k = 1;
@@ -831,9 +953,8 @@ polymul_status polymul_plan_create(polymul_plan** plan, const polymul_group* gro
       const uint64_t q64 = G.q;
       st = fill_stream(job.sp, G.a, G.b, G.c, n, &q64, 1, 1, 0, G.count, 4, &lds);
       if (st == POLYMUL_OK && split) {
-        const uint64_t scost = 4 * ((uint64_t)job.sp.r << job.sp.log2spd);
         uint32_t k = 1;
-        while (k < job.sp.nchunks && scost / k > share) k *= 2;
+        while (k < job.sp.nchunks && ci / k > share) k *= 2;
         job.sp.kparts = k;
         if (k > 1) {
           job.sp.part_ws = (void*)(uintptr_t)part_words;
@@ -844,8 +965,9 @@ polymul_status polymul_plan_create(polymul_plan** plan, const polymul_group* gro
     if (st != POLYMUL_OK) { plan_free(p); return st; }
     p->lds = std::max(p->lds, lds);
     const uint32_t jid = (uint32_t)jobs.size();
-    const uint64_t cnt = job.kind == kJobResident ? ((G.count << job.rp.log2U) + 3) / 4 * job.rp.kparts
-                                                  : G.count * job.sp.ublocks * job.sp.kparts;
+    const uint64_t cnt = job.kind == kJobSmall      ? (G.count + job.rp.slots - 1) / job.rp.slots
+                         : job.kind == kJobResident ? ((G.count << job.rp.log2U) + 3) / 4 * job.rp.kparts
+                                                    : G.count * job.sp.ublocks * job.sp.kparts;
     if (cnt + items.size() > 0xFFFFFFFFull) { plan_free(p); return POLYMUL_EUNSUPPORTED; }
     for (uint64_t i = 0; i < cnt; ++i) items.push_back(WorkItem{jid, (uint32_t)i});
     jobs.push_back(job);
@@ -1039,7 +1161,11 @@ polymul_status polymul_karatsuba_u64_workspace_size(uint64_t n, uint64_t batch, 
 polymul_status polymul_negacyclic_u64_karatsuba(const uint64_t* a, const uint64_t* b, uint64_t* c, uint64_t n,
                                                 uint64_t q, uint64_t batch, uint32_t depth, void* workspace,
                                                 uint64_t workspace_bytes, hipStream_t stream) {
-  if (q < 2) return POLYMUL_EINVAL;
+  if (q < 2 || !is_pow2(n) || n > 65536) return POLYMUL_EINVAL;
+  if (depth == 0) {
+    depth = kara_depth_for(n, batch, true);
+    if (depth == 0) return polymul_negacyclic_u64(a, b, c, n, q, batch, stream);
+  }
   uint64_t need;
   polymul_status st = kara_workspace(n, batch, depth, 8, &need, true);
   if (st != POLYMUL_OK) return st;
@@ -1077,7 +1203,8 @@ polymul_status polymul_negacyclic_u64_karatsuba(const uint64_t* a, const uint64_
   const uint64_t per_round = (uint64_t)device_cus() * (Ls == 4 ? 2 : 1);
   uint32_t runs = 1;
   double best = (double)((sblocks + per_round - 1) / per_round);
-  for (uint32_t k = 2; k <= kKaraRuns && k <= SP.nchunks; k *= 2) {
+  const uint32_t runs_max = g_kara_runs_max.load(std::memory_order_relaxed);
+  for (uint32_t k = 2; k <= runs_max && k <= SP.nchunks; k *= 2) {
     const double rounds = (double)((sblocks * k + per_round - 1) / per_round) / k;
     if (rounds < best - 1e-9) { best = rounds; runs = k; }
   }
@@ -1099,6 +1226,11 @@ polymul_status polymul_negacyclic_u64_karatsuba(const uint64_t* a, const uint64_
 polymul_status polymul_negacyclic_rns_karatsuba(const uint32_t* a, const uint32_t* b, uint32_t* c, uint64_t n,
                                                 const uint32_t* q, uint32_t L, uint64_t batch, uint32_t depth,
                                                 void* workspace, uint64_t workspace_bytes, hipStream_t stream) {
+  if (!is_pow2(n) || n > 65536 || L == 0 || L > 16) return POLYMUL_EINVAL;
+  if (depth == 0) {
+    depth = kara_depth_for(n, batch * L, false);
+    if (depth == 0) return polymul_negacyclic_rns(a, b, c, n, q, L, batch, stream);
+  }
   uint64_t need, bytes;
   polymul_status st = check_rns_karatsuba(a, b, c, n, q, L, batch, depth, &need, &bytes);
   if (st != POLYMUL_OK || batch == 0) return st;
@@ -1111,6 +1243,11 @@ polymul_status polymul_negacyclic_rns_karatsuba(const uint32_t* a, const uint32_
 polymul_status polymul_negacyclic_rns_karatsuba_noalloc(const uint32_t* a, const uint32_t* b, uint32_t* c,
                                                         uint64_t n, const uint32_t* q, uint32_t L, uint64_t batch,
                                                         uint32_t depth, hipStream_t stream) {
+  if (!is_pow2(n) || n > 65536 || L == 0 || L > 16) return POLYMUL_EINVAL;
+  if (depth == 0) {
+    depth = kara_depth_for(n, batch * L, false);
+    if (depth == 0) return polymul_negacyclic_rns(a, b, c, n, q, L, batch, stream);
+  }
   uint64_t need, bytes;
   polymul_status st = check_rns_karatsuba(a, b, c, n, q, L, batch, depth, &need, &bytes);
   if (st != POLYMUL_OK || batch == 0) return st;
@@ -1136,6 +1273,49 @@ polymul_status polymul_tune_set(uint64_t n, uint32_t L, uint32_t t) {
   }
   g_tile[ilog2(n)][L].store(t, std::memory_order_relaxed);
   return POLYMUL_OK;
+}
+
+polymul_status polymul_tune_param_set(uint32_t param, uint64_t value) {
+  switch (param) {
+    case POLYMUL_TUNE_PLAN_SHARE_PCT:
+      if (value < 10 || value > 1000) return POLYMUL_EINVAL;
+      g_plan_share_pct.store((uint32_t)value, std::memory_order_relaxed);
+      return POLYMUL_OK;
+    case POLYMUL_TUNE_PLAN_STREAM_PCT:
+      if (value < 50 || value > 400) return POLYMUL_EINVAL;
+      g_plan_stream_pct.store((uint32_t)value, std::memory_order_relaxed);
+      return POLYMUL_OK;
+    case POLYMUL_TUNE_U64_KARATSUBA_RUNS:
+      if (value != 1 && value != 2 && value != 4) return POLYMUL_EINVAL;
+      g_kara_runs_max.store((uint32_t)value, std::memory_order_relaxed);
+      return POLYMUL_OK;
+  }
+  return POLYMUL_EINVAL;
+}
+
+polymul_status polymul_tune_set_karatsuba(uint64_t n, uint64_t products, uint32_t elem_bytes, uint32_t depth) {
+  if (!is_pow2(n) || n > 65536 || products == 0 || (elem_bytes != 4 && elem_bytes != 8)) return POLYMUL_EINVAL;
+  if (depth != kNotTuned && (depth > 3 || (depth > 0 && (n >> depth) < 4))) return POLYMUL_EINVAL;
+  (elem_bytes == 8 ? g_kara64_depth : g_kara_depth)[ilog2(n)][ilog2_floor(products)].store(
+      depth, std::memory_order_relaxed);
+  return POLYMUL_OK;
+}
+
+polymul_status polymul_tune_get_karatsuba(uint64_t n, uint64_t products, uint32_t elem_bytes, uint32_t* depth) {
+  if (!is_pow2(n) || n > 65536 || products == 0 || (elem_bytes != 4 && elem_bytes != 8) || !depth)
+    return POLYMUL_EINVAL;
+  *depth = kara_depth_for(n, products, elem_bytes == 8);
+  return POLYMUL_OK;
+}
+
+polymul_status polymul_tune_param_get(uint32_t param, uint64_t* value) {
+  if (!value) return POLYMUL_EINVAL;
+  switch (param) {
+    case POLYMUL_TUNE_PLAN_SHARE_PCT: *value = g_plan_share_pct.load(std::memory_order_relaxed); return POLYMUL_OK;
+    case POLYMUL_TUNE_PLAN_STREAM_PCT: *value = g_plan_stream_pct.load(std::memory_order_relaxed); return POLYMUL_OK;
+    case POLYMUL_TUNE_U64_KARATSUBA_RUNS: *value = g_kara_runs_max.load(std::memory_order_relaxed); return POLYMUL_OK;
+  }
+  return POLYMUL_EINVAL;
 }
 
 polymul_status polymul_tune_get(uint64_t n, uint32_t L, uint32_t* t) {

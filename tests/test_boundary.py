@@ -130,12 +130,15 @@ def test_plan_group_validation():
 
 
 def test_tile_table():
-    for n, t in ((4096, 64), (4096, 128), (4096, 32), (1024, 64), (16, 16)):
+    for n, t in ((4096, 64), (4096, 128), (4096, 32), (1024, 64), (16, 16), (512, 16), (64, 16), (256, 32)):
         pm.polymul_tune_set(n, 4, t)
         assert pm.polymul_tune_get(n, 4) == t
         pm.polymul_tune_set(n, 4, 0)
-    assert pm.polymul_tune_get(4096, 4) == 64 and pm.polymul_tune_get(256, 2) == 32
-    for n, L, t in ((4096, 4, 48), (4096, 4, 256), (4096, 5, 64), (1000, 4, 32), (16, 4, 32), (64, 4, 128)):
+    # built-in: 16x16 tiles for 64..512, 32x32 at 1024, a 64-side above
+    assert pm.polymul_tune_get(4096, 4) == 64 and pm.polymul_tune_get(1024, 2) == 32
+    assert pm.polymul_tune_get(256, 2) == 16 and pm.polymul_tune_get(512, 4) == 16 and pm.polymul_tune_get(64, 3) == 16
+    for n, L, t in ((4096, 4, 48), (4096, 4, 256), (4096, 5, 64), (1000, 4, 32), (16, 4, 32), (64, 4, 128),
+                    (1024, 4, 16), (32, 4, 16)):
         with pytest.raises(pm.PolymulError):
             pm.polymul_tune_set(n, L, t)
 
@@ -150,8 +153,8 @@ def test_karatsuba_workspace_size():
     for n, L, batch, depth in ((4096, 8, 16, 2), (64, 1, 3, 1), (65536, 2, 1, 3), (32, 4, 2, 3)):
         words = batch * L * 3 ** depth * (n >> depth)
         assert pm.polymul_karatsuba_workspace_size(n, L, batch, depth) == 3 * 4 * words
-    for n, L, depth in ((4096, 8, 0), (4096, 8, 4), (16, 1, 3), (100, 1, 1), (4096, 0, 1), (4096, 17, 1),
-                        (131072, 1, 1)):
+    for n, L, depth in ((4096, 8, 4), (16, 1, 3), (100, 1, 1), (4096, 0, 1), (4096, 17, 1),
+                        (131072, 1, 1), (100, 1, 0)):
         with pytest.raises(pm.PolymulError):
             pm.polymul_karatsuba_workspace_size(n, L, 1, depth)
 
@@ -165,7 +168,10 @@ def test_karatsuba_arguments():
     assert call(k, A, B, C, 256, qp, 2, 1, 2, W, need - 1, None) == EINVAL   # workspace too small
     assert call(k, A, B, C, 256, qp, 2, 1, 2, W + 4, need, None) == EINVAL   # misaligned workspace
     assert call(k, A, B, C, 256, qp, 2, 1, 2, None, need, None) == EINVAL    # no workspace
-    assert call(k, A, B, C, 256, qp, 2, 1, 0, W, need, None) == EINVAL       # depth 0
+    # depth 0 resolves to the tuned depth (built-in: two levels at n = 4096), checked like an explicit one
+    need0 = pm.polymul_karatsuba_workspace_size(4096, 2, 1, 0)
+    assert need0 == pm.polymul_karatsuba_workspace_size(4096, 2, 1, 2)
+    assert call(k, A, B, C, 4096, qp, 2, 1, 0, W, need0 - 1, None) == EINVAL
     assert call(k, A, B, C, 256, qp, 2, 1, 4, W, 1 << 30, None) == EINVAL    # depth 4
     assert call(k, A, B, C, 8, qp, 2, 1, 2, W, need, None) == EINVAL         # n / 2^depth < 4
     assert call(k, A, B, C, 256, None, 2, 1, 2, W, need, None) == EINVAL
@@ -186,7 +192,7 @@ def test_karatsuba_noalloc_arguments():
     k = "polymul_negacyclic_rns_karatsuba_noalloc"
     assert pm.polymul_karatsuba_workspace_size(4096, 8, 256, 1) > binding.POLYMUL_NOALLOC_SCRATCH_BYTES
     assert call(k, A, B, C, 4096, qp, 8, 256, 1, None) == ESCRATCH
-    assert call(k, A, B, C, 4096, qp, 8, 1, 0, None) == EINVAL        # depth 0
+    assert call(k, A, B, C, 4096, qp, 8, 256, 0, None) == ESCRATCH    # depth 0: two levels here
     assert call(k, A, B, C, 4096, qp, 8, 1, 4, None) == EINVAL        # depth 4
     assert call(k, A, B, C, 8, qp, 8, 1, 2, None) == EINVAL           # n / 2^depth < 4
     assert call(k, A, B, C, 4096, None, 8, 1, 2, None) == EINVAL
@@ -242,7 +248,52 @@ def test_karatsuba_u64_arguments():
     k = "polymul_negacyclic_u64_karatsuba"
     assert call(k, A, B, C, 256, 17, 1, 1, W, need - 1, None) == EINVAL
     assert call(k, A, B, C, 256, 1, 1, 1, W, need, None) == EINVAL
-    assert call(k, A, B, C, 256, 17, 1, 0, W, need, None) == EINVAL
+    need3 = pm.polymul_karatsuba_u64_workspace_size(65536, 16, 3)
+    assert pm.polymul_karatsuba_u64_workspace_size(65536, 16, 0) == need3  # depth 0: three levels at n = 65536
+    assert call(k, A, B, C, 65536, 17, 16, 0, W, need3 - 1, None) == EINVAL
     assert call(k, A, B, A, 256, 17, 1, 1, W, need, None) == EALIAS
     assert call(k, A, B, C, 256, 17, 1, 1, B + 16, need, None) == EALIAS
     assert call(k, None, None, None, 256, 17, 0, 1, None, 0, None) == 0
+
+
+def test_plan_tuning_knobs():
+    assert pm.polymul_tune_param_get("plan_share_pct") == 100
+    assert pm.polymul_tune_param_get("plan_stream_pct") == 125
+    lib = pm.load_library()
+    assert lib.polymul_tune_param_set(1, 9) == EINVAL
+    assert lib.polymul_tune_param_set(1, 1001) == EINVAL
+    assert lib.polymul_tune_param_set(2, 49) == EINVAL
+    assert lib.polymul_tune_param_set(99, 100) == EINVAL
+    assert lib.polymul_tune_param_get(1, None) == EINVAL
+    assert pm.polymul_tune_param_get("u64_karatsuba_runs") == 4
+    assert lib.polymul_tune_param_set(3, 3) == EINVAL
+    pm.polymul_tune_param_set("plan_share_pct", 250)
+    assert pm.polymul_tune_param_get("plan_share_pct") == 250
+    pm.polymul_tune_param_set("plan_share_pct", 100)
+
+
+def test_karatsuba_depth_table():
+    # built-in choices, a tuned entry for one products bucket, and back
+    assert pm.polymul_tune_get_karatsuba(4096, 2048, 4) == 2
+    assert pm.polymul_tune_get_karatsuba(512, 2048, 4) == 1
+    assert pm.polymul_tune_get_karatsuba(256, 2048, 4) == 0
+    assert pm.polymul_tune_get_karatsuba(65536, 16, 8) == 3
+    assert pm.polymul_tune_get_karatsuba(16, 16, 8) == 1
+    try:
+        pm.polymul_tune_set_karatsuba(4096, 2048, 4, 3)
+        assert pm.polymul_tune_get_karatsuba(4096, 2048, 4) == 3
+        assert pm.polymul_tune_get_karatsuba(4096, 4095, 4) == 3      # same power-of-two bucket
+        assert pm.polymul_tune_get_karatsuba(4096, 4096, 4) == 2      # the next bucket is untouched
+        assert pm.polymul_tune_get_karatsuba(4096, 2048, 8) == 1      # and so are 64-bit words
+        assert pm.polymul_karatsuba_workspace_size(4096, 8, 256, 0) == pm.polymul_karatsuba_workspace_size(
+            4096, 8, 256, 3)
+        pm.polymul_tune_set_karatsuba(4096, 2048, 4, 0)
+        assert pm.polymul_karatsuba_workspace_size(4096, 8, 256, 0) == 0  # direct route: no workspace
+    finally:
+        pm.polymul_tune_set_karatsuba(4096, 2048, 4, pm.binding.KARATSUBA_BUILTIN)
+    assert pm.polymul_tune_get_karatsuba(4096, 2048, 4) == 2
+    lib = pm.load_library()
+    assert lib.polymul_tune_set_karatsuba(4096, 1, 4, 4) == EINVAL
+    assert lib.polymul_tune_set_karatsuba(8, 1, 4, 2) == EINVAL   # n / 2^depth < 4
+    assert lib.polymul_tune_set_karatsuba(4096, 0, 4, 1) == EINVAL
+    assert lib.polymul_tune_set_karatsuba(4096, 1, 2, 1) == EINVAL

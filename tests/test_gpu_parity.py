@@ -153,3 +153,4 @@ def test_workload3_groups_full():
     w = inputs.make_workload(3)
     for g in w.groups:
         _check(pm.polymul_negacyclic, g.a, g.b, g.q)
+

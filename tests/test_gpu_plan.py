@@ -158,3 +158,36 @@ def test_plan_back_to_back_replays(flags):
             assert np.array_equal(got, wv), f"n={n}: " + mismatch_report(got, wv)
     for plan in plans:
         plan.close()
+
+
+def test_plan_small_moduli_limb_counts():
+    """Groups whose moduli need two or three int8 limbs run with that many (one
+    grouped launch mixing 2-, 3- and 4-limb jobs, split items included)."""
+    rng = np.random.Generator(np.random.PCG64(23))
+    specs = [(256, 3329, 300), (1024, 3329, 40), (4096, 3329, 2), (2048, (1 << 24) - 3, 9),
+             (4096, 12289, 1), (512, 1068236801, 17), (8192, 7681, 1)]
+    groups, refs = [], []
+    for n, q, count in specs:
+        a = rng.integers(0, q, size=(count, n), dtype=np.uint64).astype(np.uint32)
+        b = rng.integers(0, q, size=(count, n), dtype=np.uint64).astype(np.uint32)
+        da, db = to_dev(a), to_dev(b)
+        groups.append((da, db, torch.zeros_like(da), n, q))
+        refs.append((a, b, q))
+    for share, stream in ((100, 125), (10, 400), (1000, 50)):
+        pm.polymul_tune_param_set("plan_share_pct", share)
+        pm.polymul_tune_param_set("plan_stream_pct", stream)
+        try:
+            plan = pm.Plan(groups)
+        finally:
+            pm.polymul_tune_param_set("plan_share_pct", 100)
+            pm.polymul_tune_param_set("plan_stream_pct", 125)
+        for rep in range(2):
+            for g in groups:
+                g[2].zero_()
+            plan.execute()
+            torch.cuda.synchronize()
+            for (da, db, dc, n, q), (a, b, _) in zip(groups, refs):
+                got = to_host(dc, np.uint32)
+                wv = oracle.negacyclic(a, b, q)
+                assert np.array_equal(got, wv), f"share {share}, replay {rep}, n={n}, q={q}: " + mismatch_report(got, wv)
+        plan.close()
