@@ -152,4 +152,35 @@ __host__ __device__ __forceinline__ void digits_pm32(const uint32_t (&x)[4], uin
   }
 }
 
+// ---------------------------------------------------------------------------
+// Small moduli (the residue-number-system path, paper Sec. 2.4 and 2.6).
+// ---------------------------------------------------------------------------
+// The centred residue of v mod m as an int32 in [-128, 127], for |v| < 2^31 and
+// 2 <= m <= 256.  Write v = 2^16 vh + vl (vl in [0, 2^16)); with R = 2^16 mod m,
+// x = vh R + vl = v (mod m) and |x| < 2^23 + 2^16, so x is exact in fp32.  k =
+// rint of the rounded fp32 quotient x (1/m) and r = x - k m by one fma are exact
+// integers, r = v (mod m).  The quotient is off by less than 1.01 / m, so k is off
+// by at most one and only when the exact centred residue lies within 1.01 of
+// +-m/2: |r| <= m/2 + 1, an int8 for m <= 253; 255 needs r = 128 folded to -127;
+// for 256 the residue is the low byte of v.
+// The same for |x| < 2^23 + 2^16 (m < 256), the range vh R + vl takes.
+__host__ __device__ __forceinline__ int32_t centred_mod_small(int32_t x, uint32_t m, float mf, float invm) {
+  const float xf = (float)x;
+  const float kf = rintf(xf * invm);
+  int32_t r = (int32_t)fmaf(-kf, mf, xf);
+  if (m > 253 && r > 127) r -= (int32_t)m;
+  return r;
+}
+__host__ __device__ __forceinline__ int32_t residue_centred(int32_t v, uint32_t m, int32_t r16, float mf,
+                                                            float invm) {
+  if (m == 256) return (int32_t)(int8_t)(uint8_t)v;
+  const int32_t vh = v >> 16, vl = v & 0xFFFF;
+#if defined(__HIP_DEVICE_COMPILE__)
+  const int32_t x = __mul24(vh, r16) + vl;  // both factors fit 24 bits: the full-rate multiply
+#else
+  const int32_t x = vh * r16 + vl;
+#endif
+  return centred_mod_small(x, m, mf, invm);
+}
+
 }  // namespace pm

@@ -15,9 +15,12 @@
 //
 // Reconstruction (ConvertMatrix): s_c = (T_c mod m_c) (M/m_c)^-1 mod m_c gives
 // X' = sum_c s_c M/m_c = X + kappa M with kappa = round(sum_c s_c / m_c), since
-// |X| / M < 1/2.  The sum of fractions is taken in fp32; M > 2B (1 + 2^-16)
-// keeps it at least 2^-17 away from a rounding boundary, far more than the
-// fp32 error of at most 11 * 2^-23.  Then c_j = (sum_c s_c (M/m_c mod q) -
+// |X| / M < 1/2.  The sum of fractions is taken in fp32: M > 2B (1 + 2^-16)
+// keeps the true sum at least 2^-17 (about 7.6e-6) away from a rounding
+// boundary, and with u = 2^-24 the fp32 value is within (2C + C(C+1)/2 + C + 1) u
+// of it -- two roundings per term (1/m and the product), one per running sum
+// (below k after k terms) and the final + 0.5 -- at most 100 u (about 6.0e-6) for
+// C <= 11, so kappa is exact.  Then c_j = (sum_c s_c (M/m_c mod q) -
 // kappa (M mod q)) mod q.
 #pragma once
 #include "pm_mfma32.h"
@@ -36,6 +39,8 @@ struct CrtConsts {
   uint32_t yp[kMaxCh];         // floor(y 2^32 / m): Shoup's companion of y
   uint32_t oy[kMaxCh];         // (2^31 y) mod m
   float invm[kMaxCh];          // 1 / m
+  float mf[kMaxCh];            // m
+  int32_t r16[kMaxCh];         // 2^16 mod m
   uint32_t w[kMaxQC][kMaxCh];  // (M / m) mod q
   uint32_t Mq[kMaxQC];         // M mod q
 };
@@ -67,63 +72,95 @@ __device__ __forceinline__ int32_t centred_lift(uint32_t x, uint32_t q) {
   return x > (q >> 1) ? (int32_t)(x - q) : (int32_t)x;
 }
 
-// Residue planes of four consecutive words (v[k] already lifted): plane c gets
-// the dword whose byte k is the residue of v[order[k]].
-template <int C>
-__device__ __forceinline__ void crt_store4(const CrtConsts& K, uint8_t* base, uint32_t plane, uint32_t off,
-                                           const int32_t (&v)[4], bool store_neg, uint8_t* nbase, uint32_t noff) {
-#pragma unroll
-  for (int c = 0; c < C; ++c) {
-    const uint32_t m = K.m[c], mg = K.magic[c], of = K.off[c];
-    const uint32_t d = centred_byte(v[0], m, mg, of) | (centred_byte(v[1], m, mg, of) << 8) |
-                       (centred_byte(v[2], m, mg, of) << 16) | (centred_byte(v[3], m, mg, of) << 24);
-    *(uint32_t*)(base + c * plane + off) = d;
-    if (store_neg) *(uint32_t*)(nbase + c * plane + noff) = neg_bytes(d);
-  }
-}
+// One staging pass of the wave kernel: each thread loads up to kStageItems word
+// groups (a's, into the reversed ext planes, or b's, into the B rows), lifts
+// them to centred integers and notes where their residue dwords go (a dword and,
+// where the window or the rows need it, its byte-wise negation); then the
+// channels are taken one at a time, so that only one channel's constants are
+// live while every item's four residues are formed and stored.
+constexpr int kStageItems = 4;
 
-// One staged item (n >= 4): a's word group j into the reversed ext planes (and
-// its negated copy inside the window), or b's word group into rows vs (+) and
-// vs - r (-).
-template <int C>
-__device__ __forceinline__ void crt_item_store(const Mfma32Params& P, const CrtConsts& K, const GroupInfo& gi,
-                                               uint8_t* smem, uint32_t i, uint4 x) {
+template <int C, int NT>
+__device__ __forceinline__ void crt_stage_pass(const Mfma32Params& P, const CrtConsts& K, const GroupInfo& gi,
+                                               uint8_t* smem, uint32_t base, uint32_t nitems) {
   const uint32_t lper = P.log2n - 1, quarter = P.n >> 2;
-  const uint32_t s = i >> lper, j = i & ((1u << lper) - 1);
-  const ModQ32& m = P.mods[slot_li(gi, s)];
-  uint8_t* slot = smem + s * P.slot_bytes;
-  if (j < quarter) {
-    // reversed: byte k of dword (E+1)/4 - 1 - j holds ext[4j + 3 - k]
-    const int32_t v[4] = {centred_lift(reduce_u32(x.w, m), m.q), centred_lift(reduce_u32(x.z, m), m.q),
-                          centred_lift(reduce_u32(x.y, m), m.q), centred_lift(reduce_u32(x.x, m), m.q)};
-    const uint32_t dw = ((P.E + 1) >> 2) - 1 - j;
-    const uint32_t dwn = dw + quarter;
-    crt_store4<C>(K, slot, P.a_plane, dw * 4, v, dwn < (P.a_plane >> 2), slot, dwn * 4);
-  } else {
-    const uint32_t e = j - quarter;
-    const int vs = (int)(e >> (P.log2t - 2)), wd = (int)(e & ((P.t >> 2) - 1));
-    const int32_t v[4] = {centred_lift(reduce_u32(x.x, m), m.q), centred_lift(reduce_u32(x.y, m), m.q),
-                          centred_lift(reduce_u32(x.z, m), m.q), centred_lift(reduce_u32(x.w, m), m.q)};
-    uint8_t* bbase = slot + C * P.a_plane;
-    const int rp = vs - gi.v_lo, rn = vs - (int)P.r - gi.v_lo;
-    const bool pos = rp >= 0 && rp < (int)P.b_rows, neg = rn >= 0 && rn < (int)P.b_rows;
-    if (pos) crt_store4<C>(K, bbase, P.b_plane, rp * P.b_rowstride + wd * 4, v, neg, bbase,
-                           neg ? rn * P.b_rowstride + wd * 4 : 0);
-    else if (neg) {
-      const int32_t nv[4] = {-v[0], -v[1], -v[2], -v[3]};
-      crt_store4<C>(K, bbase, P.b_plane, rn * P.b_rowstride + wd * 4, nv, false, bbase, 0);
+  uint4 pf[kStageItems];
+#pragma unroll
+  for (int k = 0; k < kStageItems; ++k) {
+    const uint32_t i = base + threadIdx.x + k * NT;
+    const uint4* src = i < nitems ? item_src(P, gi, i) : nullptr;
+    pf[k] = src ? *src : make_uint4(0, 0, 0, 0);
+  }
+  int32_t v[kStageItems][4];
+  uint32_t dst1[kStageItems], dst2[kStageItems], pstride[kStageItems], flags[kStageItems];
+#pragma unroll
+  for (int k = 0; k < kStageItems; ++k) {
+    const uint32_t i = base + threadIdx.x + k * NT;
+    flags[k] = 0;
+    dst1[k] = dst2[k] = 0;
+    pstride[k] = 0;
+    v[k][0] = v[k][1] = v[k][2] = v[k][3] = 0;
+    if (i >= nitems) continue;
+    const uint32_t s = i >> lper, j = i & ((1u << lper) - 1);
+    const ModQ32& m = P.mods[slot_li(gi, s)];
+    const uint4 x = pf[k];
+    const uint32_t slot = s * P.slot_bytes;
+    if (j < quarter) {
+      // reversed: byte k of dword (E+1)/4 - 1 - j holds ext[4j + 3 - k]; the negated
+      // copy n/4 dwords further where the window reaches it
+      v[k][0] = centred_lift(reduce_u32(x.w, m), m.q);
+      v[k][1] = centred_lift(reduce_u32(x.z, m), m.q);
+      v[k][2] = centred_lift(reduce_u32(x.y, m), m.q);
+      v[k][3] = centred_lift(reduce_u32(x.x, m), m.q);
+      const uint32_t dw = ((P.E + 1) >> 2) - 1 - j, dwn = dw + quarter;
+      dst1[k] = slot + dw * 4;
+      dst2[k] = slot + dwn * 4;
+      pstride[k] = P.a_plane;
+      flags[k] = 1u | (dwn < (P.a_plane >> 2) ? 2u : 0u);
+    } else {
+      const uint32_t e = j - quarter;
+      const int vs = (int)(e >> (P.log2t - 2)), wd = (int)(e & ((P.t >> 2) - 1));
+      v[k][0] = centred_lift(reduce_u32(x.x, m), m.q);
+      v[k][1] = centred_lift(reduce_u32(x.y, m), m.q);
+      v[k][2] = centred_lift(reduce_u32(x.z, m), m.q);
+      v[k][3] = centred_lift(reduce_u32(x.w, m), m.q);
+      const uint32_t bbase = slot + C * P.a_plane;
+      const int rp = vs - gi.v_lo, rn = vs - (int)P.r - gi.v_lo;
+      dst1[k] = bbase + (uint32_t)(rp * (int)P.b_rowstride + wd * 4);
+      dst2[k] = bbase + (uint32_t)(rn * (int)P.b_rowstride + wd * 4);
+      pstride[k] = P.b_plane;
+      flags[k] = (rp >= 0 && rp < (int)P.b_rows ? 1u : 0u) | (rn >= 0 && rn < (int)P.b_rows ? 2u : 0u);
+    }
+  }
+#pragma unroll 1
+  for (int c = 0; c < C; ++c) {
+    const uint32_t m = K.m[c];
+    const int32_t r16 = K.r16[c];
+    const float mf = K.mf[c], im = K.invm[c];
+#pragma unroll
+    for (int k = 0; k < kStageItems; ++k) {
+      if (!flags[k]) continue;
+      const uint32_t r0 = (uint32_t)residue_centred(v[k][0], m, r16, mf, im);
+      const uint32_t r1 = (uint32_t)residue_centred(v[k][1], m, r16, mf, im);
+      const uint32_t r2 = (uint32_t)residue_centred(v[k][2], m, r16, mf, im);
+      const uint32_t r3 = (uint32_t)residue_centred(v[k][3], m, r16, mf, im);
+      const uint32_t d = __builtin_amdgcn_perm(__builtin_amdgcn_perm(r3, r2, 0x0c0c0400u),
+                                               __builtin_amdgcn_perm(r1, r0, 0x0c0c0400u), 0x05040100u);
+      uint8_t* plane = smem + c * pstride[k];
+      if (flags[k] & 1u) *(uint32_t*)(plane + dst1[k]) = d;
+      if (flags[k] & 2u) *(uint32_t*)(plane + dst2[k]) = neg_bytes(d);
     }
   }
 }
 
-// n < 4: the planes of one product byte by byte.
-template <int C>
+// n < 4: the planes of one product byte by byte (NT threads).
+template <int C, int NT>
 __device__ __forceinline__ void crt_stage_small(const Mfma32Params& P, const CrtConsts& K, uint8_t* slot,
                                                 uint64_t gprod, const ModQ32& m, int v_lo) {
   const uint32_t* A = P.a + gprod * P.n;
   const uint32_t* B = P.b + gprod * P.n;
   const int n = (int)P.n, t = (int)P.t, r = (int)P.r;
-  for (int p = threadIdx.x; p < (int)P.a_plane; p += kThreads) {
+  for (int p = threadIdx.x; p < (int)P.a_plane; p += NT) {
     const int idx = (int)P.E - p;
     int32_t v = 0;
     if (idx >= 0 && idx < n) v = centred_lift(reduce_u32(A[idx], m), m.q);
@@ -133,7 +170,7 @@ __device__ __forceinline__ void crt_stage_small(const Mfma32Params& P, const Crt
   }
   uint8_t* bbase = slot + C * P.a_plane;
   const int nb = (int)(P.b_rows * P.rowlen);
-  for (int e = threadIdx.x; e < nb; e += kThreads) {
+  for (int e = threadIdx.x; e < nb; e += NT) {
     const int row = e / (int)P.rowlen, ww = e - row * (int)P.rowlen;
     const int v_row = v_lo + row;
     int32_t v = 0;
@@ -147,166 +184,265 @@ __device__ __forceinline__ void crt_stage_small(const Mfma32Params& P, const Crt
   }
 }
 
-// One K-step: channel by channel, its MFMA, its B refill, then its next A
-// fragment aligned from runs read a step earlier and the runs after that read.
+// ---------------------------------------------------------------------------
+// One residue channel per wave (the paper's independent instance per modulus,
+// Sec. 2.4): a workgroup holds the residue planes of a group of four 32x32
+// output tiles and runs 4 ceil(C/4) waves.  Wave w < 4 floor(C/4) computes all
+// four tiles of channel w over the whole K range; the R = C mod 4 remaining
+// channels are spread over the last four waves (R = 1: one channel cut into four
+// K quarters; R = 2: two channels in K halves; R = 3: one channel per wave, the
+// fourth wave idle), so that every SIMD carries the same matrix work.  Sharing a
+// channel, the four tiles reuse fragments: where the group is one product in
+// 2 x 2 tiles, each K-step reads two A and two B fragments for four MFMAs (18
+// bytes of LDS per lane and MFMA against 36 when every MFMA reads its own pair).
+// After the K loop the channels meet in LDS: the waves of a cut channel add their
+// int32 partial sums, each channel's (T mod m) (M/m)^-1 mod m goes in as a byte
+// per output, and all threads then rebuild the outputs by the CRT.
+// ---------------------------------------------------------------------------
 template <int C>
-__device__ __forceinline__ void crt_step(v16i (&acc)[C], const v4i (&a)[C], v4i (&an)[C], uint32_t (&araw)[C][5],
-                                         uint32_t sh_next, const uint8_t* aplane, uint32_t a_plane, int S_after,
-                                         v4i (&b)[C], const uint8_t* bplane, uint32_t b_plane, int boff_next) {
-#pragma unroll
-  for (int c = 0; c < C; ++c) {
-    acc[c] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[c], b[c], acc[c], 0, 0, 0);
-    b[c] = *(const v4i*)(bplane + c * b_plane + boff_next);
-    an[c][0] = (int)__builtin_amdgcn_alignbyte(araw[c][1], araw[c][0], sh_next);
-    an[c][1] = (int)__builtin_amdgcn_alignbyte(araw[c][2], araw[c][1], sh_next);
-    an[c][2] = (int)__builtin_amdgcn_alignbyte(araw[c][3], araw[c][2], sh_next);
-    an[c][3] = (int)__builtin_amdgcn_alignbyte(araw[c][4], araw[c][3], sh_next);
-    const uint32_t* p = (const uint32_t*)(aplane + c * a_plane) + (S_after >> 2);
-#pragma unroll
-    for (int k = 0; k < 5; ++k) araw[c][k] = p[k];
-    __builtin_amdgcn_sched_barrier(0);
+struct CrtWaves {
+  static constexpr int kFull = 4 * (C / 4);            // waves with a whole channel
+  static constexpr int kRest = C - kFull;               // channels left for the last four waves
+  static constexpr int kWaves = kFull + (kRest ? 4 : 0);
+  static constexpr int kThreadsW = 64 * kWaves;
+  // channel, part and number of parts of wave w (channel -1: idle)
+  __device__ static void role(int w, int& ch, int& part, int& parts) {
+    if (w < kFull) { ch = w; part = 0; parts = 1; return; }
+    const int x = w - kFull;
+    if (kRest == 1) { ch = kFull; part = x; parts = 4; }
+    else if (kRest == 2) { ch = kFull + x / 2; part = x % 2; parts = 2; }
+    else { ch = x < 3 ? kFull + x : -1; part = 0; parts = 1; }
   }
+};
+
+// LDS of the combine step, laid over the (no longer read) residue planes:
+// the s bytes, dword [c][unit][blk][lane] holding the four outputs z = 8 blk + 4 g
+// + e (e = 0..3) of the lane's column; then, for cut channels, the int32 partial
+// sums of parts 1.., [slot][unit][rr][lane].
+constexpr uint32_t kCrtSBytes = 4 * 4 * 64 * 4;    // per channel: 4 units x 4 blk x 64 lanes dwords
+constexpr uint32_t kCrtPartBytes = 4 * 16 * 64 * 4;  // per part: 4 units x 16 values x 64 lanes int32
+
+template <int C>
+__host__ __device__ constexpr uint32_t crt_combine_bytes() {
+  return C * kCrtSBytes + (C % 4 == 1 ? 3 : C % 4 == 2 ? 2 : 0) * kCrtPartBytes;
 }
 
-// One 32x32 output tile: all channels over the whole K loop.
-template <int C>
-__device__ __forceinline__ void crt_tile(const Mfma32Params& P, const uint8_t* aplane, const uint8_t* bplane, int z0,
-                                         int u0, int v_lo, v16i (&acc)[C]) {
+// A unit (one 32x32 tile) of the group: its slot, tile offsets, validity.
+struct CrtUnit {
+  int slot, z0, u0;
+  bool valid;
+};
+
+__device__ __forceinline__ CrtUnit crt_unit(const Mfma32Params& P, const GroupInfo& gi, uint64_t grp, int i) {
+  const uint64_t total_units = P.nprod << P.log2U;
+  const uint32_t U = 1u << P.log2U;
+  const uint64_t unit = grp * 4 + (uint64_t)i;
+  CrtUnit cu;
+  cu.valid = unit < total_units;
+  const uint64_t prod = unit >> P.log2U;
+  const uint32_t tile = (uint32_t)(unit & (U - 1));
+  cu.slot = cu.valid ? (int)(prod - gi.first) : 0;
+  cu.z0 = 32 * (int)(tile % P.tz);
+  cu.u0 = 32 * (int)(tile / P.tz);
+  return cu;
+}
+
+// The K loop of one channel over K-steps [st_lo, st_hi) for the group's four
+// units.  SHARE22: one product in 2 x 2 tiles (units 0..3 = (z,u) = (0,0),
+// (1,0), (0,1), (1,1)): A fragments by z, B fragments by u.  The next step's
+// fragments are read while the current step's MFMAs run.
+template <bool SHARE22>
+__device__ __forceinline__ void crt_channel_loop(const Mfma32Params& P, const uint8_t* smem, int ch, int C,
+                                                 const CrtUnit (&un)[4], int v_lo, int st_lo, int st_hi,
+                                                 v16i (&acc)[4]) {
   const int lane = threadIdx.x & 63;
   const int zl = lane & 31, g = lane >> 5;
-  const int S0 = (int)P.E - (z0 + zl) + 16 * g;
-  const int B0 = (u0 + zl - v_lo) * (int)P.b_rowstride + 16 * g;
-  const int steps = (int)(P.r << P.log2spd);
   const int rs = (int)P.b_rowstride;
-  const uint32_t a_plane = P.a_plane, b_plane = P.b_plane;
+  constexpr int NA = SHARE22 ? 2 : 4;  // A fragments per K-step (units 0..NA-1)
+  constexpr int NB = SHARE22 ? 2 : 4;  // B fragments per K-step (units 0, 2 when shared)
+  const uint32_t* ap[NA];
+  const uint8_t* bp[NB];
+  int Sb[NA];
 #pragma unroll
-  for (int c = 0; c < C; ++c) acc[c] = v16i{};
-  auto S_of = [&](int st) { return S0 - ((st >> P.log2spd) << P.log2t) + ((st & (P.spd - 1)) << 5); };
-  auto B_of = [&](int st) { return B0 - (st >> P.log2spd) * rs + ((st & (P.spd - 1)) << 5); };
-  auto clamp = [&](int st) { return st < steps ? st : steps - 1; };
-  uint32_t araw[C][5];
-  v4i a0[C], a1[C], b[C];
-  const int S_first = S_of(0);
-  araw_load<C>(araw, aplane, a_plane, S_first);
-  b_load<C>(b, bplane, b_plane, B_of(0));
-  a_align<C>(a0, araw, (uint32_t)(S_first & 3));
-  araw_load<C>(araw, aplane, a_plane, S_of(clamp(1)));
-  int st = 0;
-  for (; st + 1 < steps; st += 2) {
-    crt_step<C>(acc, a0, a1, araw, (uint32_t)(S_of(st + 1) & 3), aplane, a_plane, S_of(clamp(st + 2)), b, bplane,
-                b_plane, B_of(st + 1));
-    crt_step<C>(acc, a1, a0, araw, (uint32_t)(S_of(clamp(st + 2)) & 3), aplane, a_plane, S_of(clamp(st + 3)), b,
-                bplane, b_plane, B_of(clamp(st + 2)));
+  for (int i = 0; i < NA; ++i) {
+    const uint8_t* slot = smem + un[i].slot * P.slot_bytes;
+    ap[i] = (const uint32_t*)(slot + ch * P.a_plane);
+    Sb[i] = (int)P.E - (un[i].z0 + zl) + 16 * g;
   }
-  if (st < steps)
-    crt_step<C>(acc, a0, a1, araw, (uint32_t)(S_of(st) & 3), aplane, a_plane, S_of(st), b, bplane, b_plane,
-                B_of(st));
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    const int u = SHARE22 ? 2 * j : j;
+    const uint8_t* slot = smem + un[u].slot * P.slot_bytes;
+    bp[j] = slot + C * P.a_plane + ch * P.b_plane + (un[u].u0 + zl - v_lo) * rs + 16 * g;
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) acc[i] = v16i{};
+  if (st_lo >= st_hi) return;
+  auto soff = [&](int st) { return -((st >> P.log2spd) << P.log2t) + ((st & (P.spd - 1)) << 5); };
+  auto boff = [&](int st) { return -(st >> P.log2spd) * rs + ((st & (P.spd - 1)) << 5); };
+  uint32_t x[NA][5];
+  v4i b[NB];
+  auto load = [&](int st) {
+    const int so = soff(st), bo = boff(st);
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const uint32_t* p = ap[i] + ((Sb[i] + so) >> 2);
+#pragma unroll
+      for (int k = 0; k < 5; ++k) x[i][k] = p[k];
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) b[j] = *(const v4i*)(bp[j] + bo);
+  };
+  load(st_lo);
+  for (int st = st_lo; st < st_hi; ++st) {
+    v4i a[NA], bc[NB];
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const uint32_t sh = (uint32_t)((Sb[i] + soff(st)) & 3);
+      a[i][0] = (int)__builtin_amdgcn_alignbyte(x[i][1], x[i][0], sh);
+      a[i][1] = (int)__builtin_amdgcn_alignbyte(x[i][2], x[i][1], sh);
+      a[i][2] = (int)__builtin_amdgcn_alignbyte(x[i][3], x[i][2], sh);
+      a[i][3] = (int)__builtin_amdgcn_alignbyte(x[i][4], x[i][3], sh);
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) bc[j] = b[j];
+    // the last step re-reads its own fragments (in bounds, unused)
+    load(st + 1 < st_hi ? st + 1 : st);
+    if constexpr (SHARE22) {
+      acc[0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[0], bc[0], acc[0], 0, 0, 0);
+      acc[1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[1], bc[0], acc[1], 0, 0, 0);
+      acc[2] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[0], bc[1], acc[2], 0, 0, 0);
+      acc[3] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[1], bc[1], acc[3], 0, 0, 0);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc[i] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], bc[i], acc[i], 0, 0, 0);
+    }
+  }
 }
 
-// Reconstruction of the 16 outputs a lane holds, then the stores.  Per channel,
-// s = (T mod m) y mod m is one Shoup product: for the 32-bit word T + 2^31 and
+// s = (T mod m) y mod m as one Shoup product: for the 32-bit word T + 2^31 and
 // y < m, (T + 2^31) y - floor((T + 2^31) yp / 2^32) m lies in [0, 2m), and the
-// precomputed (2^31 y) mod m removes the offset.  The running sum
-// lift + sum_c s w_c - kappa (M mod q) stays in (2^62 - 2^36, 2^62 + 2^44 + q).
-template <int C>
-__device__ __forceinline__ void crt_epilogue(const Mfma32Params& P, const CrtConsts& K, uint64_t gprod, uint32_t li,
-                                             int z0, int u0, const v16i (&acc)[C]) {
-  const ModQ32 m = P.mods[li];
-  const int lane = threadIdx.x & 63;
-  const int g = lane >> 5;
-  const int u = u0 + (lane & 31);
-  uint32_t mc[C], yv[C], yp[C], oy[C], wv[C];
-  float im[C];
-#pragma unroll
-  for (int c = 0; c < C; ++c) {
-    mc[c] = K.m[c];
-    yv[c] = K.y[c];
-    yp[c] = K.yp[c];
-    oy[c] = K.oy[c];
-    wv[c] = K.w[li][c];
-    im[c] = K.invm[c];
+// precomputed (2^31 y) mod m removes the offset.
+__device__ __forceinline__ uint32_t crt_s(int32_t T, uint32_t m, uint32_t y, uint32_t yp, uint32_t oy) {
+  const uint32_t tu = (uint32_t)T + 0x80000000u;
+  uint32_t su = tu * y - __umulhi(tu, yp) * m;
+  su = min(su, su - m);
+  return su >= oy ? su - oy : su + m - oy;
+}
+
+template <int C, bool SMALL, bool SHARE22>
+__global__ __launch_bounds__(CrtWaves<C>::kThreadsW)
+void crt_wave_kernel(const Mfma32Params P, const CrtConsts K) {
+  constexpr int NT = CrtWaves<C>::kThreadsW;
+  extern __shared__ __align__(16) uint8_t smem[];
+  const uint64_t grp = blockIdx.x;
+  const GroupInfo gi = group_info(P, grp);
+  // ---- stage the residue planes of the group's products
+  if constexpr (SMALL) {
+    for (uint32_t s = 0; s < gi.nslots; ++s)
+      crt_stage_small<C, NT>(P, K, smem + s * P.slot_bytes, slot_gp(gi, s), P.mods[slot_li(gi, s)], gi.v_lo);
+  } else {
+    const uint32_t nitems = gi.nslots * (P.n >> 1);
+    for (uint32_t base = 0; base < nitems; base += kStageItems * NT) {
+      crt_stage_pass<C, NT>(P, K, gi, smem, base, nitems);
+    }
+    stage_zero_fill<C, NT>(P, gi, smem);
   }
-  const uint32_t Mq = K.Mq[li];
-  uint32_t out[16];
-  auto reconstruct = [&](auto reduce) {
+  __syncthreads();
+
+  // ---- this wave's channel over its share of K
+  const int wave = (int)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  int ch, part, parts;
+  CrtWaves<C>::role(wave, ch, part, parts);
+  CrtUnit un[4];
 #pragma unroll
-    for (int rr = 0; rr < 16; ++rr) {
+  for (int i = 0; i < 4; ++i) un[i] = crt_unit(P, gi, grp, i);
+  v16i acc[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) acc[i] = v16i{};
+  if (ch >= 0) {
+    const int steps = (int)(P.r << P.log2spd);
+    const int st_lo = part * steps / parts, st_hi = (part + 1) * steps / parts;
+    crt_channel_loop<SHARE22>(P, smem, ch, C, un, gi.v_lo, st_lo, st_hi, acc);
+  }
+  __syncthreads();  // the residue planes are read for the last time
+
+  // ---- cut channels: parts 1.. leave their partial sums, part 0 adds them
+  uint32_t* sb = (uint32_t*)smem;                        // [C][4 units][4 blk][64 lanes]
+  int32_t* parts_lds = (int32_t*)(smem + C * kCrtSBytes);  // [slot][4 units][16][64 lanes]
+  if (ch >= 0 && part > 0) {
+    const int slot = CrtWaves<C>::kRest == 1 ? part - 1 : (ch - CrtWaves<C>::kFull);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int rr = 0; rr < 16; ++rr) parts_lds[((slot * 4 + i) * 16 + rr) * 64 + lane] = acc[i][rr];
+  }
+  __syncthreads();
+  if (ch >= 0 && part == 0) {
+    if (parts > 1) {
+      for (int pp = 1; pp < parts; ++pp) {
+        const int slot = CrtWaves<C>::kRest == 1 ? pp - 1 : (ch - CrtWaves<C>::kFull);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int rr = 0; rr < 16; ++rr) acc[i][rr] += parts_lds[((slot * 4 + i) * 16 + rr) * 64 + lane];
+      }
+    }
+    const uint32_t m = K.m[ch], y = K.y[ch], yp = K.yp[ch], oy = K.oy[ch];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int blk = 0; blk < 4; ++blk) {
+        uint32_t w = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) w |= crt_s(acc[i][4 * blk + e], m, y, yp, oy) << (8 * e);
+        sb[((ch * 4 + i) * 4 + blk) * 64 + lane] = w;
+      }
+  }
+  __syncthreads();
+
+  // ---- reconstruction: thread -> (unit, blk, lane) word groups, four outputs each.
+  // X' = sum_c s_c M/m_c = X + kappa M with kappa = round(sum_c s_c / m_c), since
+  // |X| / M < 1/2; the fp32 sum is within about 100 2^-24 of the true fraction
+  // (C <= 11), inside the 2^-17 margin the moduli leave, so kappa is exact.
+  for (int idx = threadIdx.x; idx < 4 * 4 * 64; idx += NT) {
+    const int i = idx >> 8, blk = (idx >> 6) & 3, ln = idx & 63;
+    const CrtUnit ui = crt_unit(P, gi, grp, i);  // recomputed: a dynamic index into un[] would go to scratch
+    if (!ui.valid) continue;
+    const int u = ui.u0 + (ln & 31);
+    const int zb = ui.z0 + 8 * blk + 4 * (ln >> 5);
+    if (u >= (int)P.r || zb >= (int)P.t) continue;
+    uint32_t li;
+    const uint64_t gprod = global_product(P, gi.first + (uint64_t)ui.slot, &li);
+    const ModQ32 mq = P.mods[li];
+    uint32_t sw[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) sw[c] = sb[((c * 4 + i) * 4 + blk) * 64 + ln];
+    uint32_t out[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
       float f = 0.0f;
-      uint64_t x = m.lift;
+      uint64_t x = mq.lift;
 #pragma unroll
       for (int c = 0; c < C; ++c) {
-        const uint32_t tu = (uint32_t)acc[c][rr] + 0x80000000u;
-        uint32_t su = tu * yv[c] - __umulhi(tu, yp[c]) * mc[c];
-        su = min(su, su - mc[c]);
-        const uint32_t sc = su >= oy[c] ? su - oy[c] : su + mc[c] - oy[c];
-        f += (float)sc * im[c];
-        x += (uint64_t)sc * wv[c];
+        const uint32_t sc = (sw[c] >> (8 * e)) & 0xFFu;
+        f += (float)sc * K.invm[c];
+        x += (uint64_t)sc * K.w[li][c];
       }
       const uint32_t kappa = (uint32_t)floorf(f + 0.5f);
-      x -= (uint64_t)kappa * Mq;
-      out[rr] = reduce(x);
+      x -= (uint64_t)kappa * K.Mq[li];
+      out[e] = mq.q < 0x80000000u ? reduce_u64_q31(x, mq.mu, mq.q) : reduce_u64(x, mq);
     }
-  };
-  if (m.q < 0x80000000u) reconstruct([&](uint64_t x) { return reduce_u64_q31(x, m.mu, m.q); });
-  else reconstruct([&](uint64_t x) { return reduce_u64(x, m); });
-  if (u >= (int)P.r) return;
-  uint32_t* Cout = P.c + gprod * P.n;
-#pragma unroll
-  for (int blk = 0; blk < 4; ++blk) {
-    const int zb = z0 + 8 * blk + 4 * g;
+    uint32_t* Cout = P.c + gprod * P.n + (size_t)u * P.t;
     if (zb + 3 < (int)P.t) {
-      *(uint4*)(Cout + (size_t)u * P.t + zb) =
-          make_uint4(out[4 * blk], out[4 * blk + 1], out[4 * blk + 2], out[4 * blk + 3]);
+      *(uint4*)(Cout + zb) = make_uint4(out[0], out[1], out[2], out[3]);
     } else {
 #pragma unroll
       for (int e = 0; e < 4; ++e)
-        if (zb + e < (int)P.t) Cout[(size_t)u * P.t + zb + e] = out[4 * blk + e];
+        if (zb + e < (int)P.t) Cout[zb + e] = out[e];
     }
   }
-}
-
-// One group of four 32x32 tiles (as the limb kernel's groups), C residue planes per operand.
-template <int C, bool SMALL>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1)))
-void crt_group_kernel(const Mfma32Params P, const CrtConsts K) {
-  extern __shared__ __align__(16) uint8_t smem[];
-  const uint64_t grp = blockIdx.x;
-  const uint64_t total_units = P.nprod << P.log2U;
-  const uint32_t U = 1u << P.log2U;
-  const GroupInfo gi = group_info(P, grp);
-  if constexpr (SMALL) {
-    for (uint32_t s = 0; s < gi.nslots; ++s)
-      crt_stage_small<C>(P, K, smem + s * P.slot_bytes, slot_gp(gi, s), P.mods[slot_li(gi, s)], gi.v_lo);
-  } else {
-    const uint32_t nitems = gi.nslots * (P.n >> 1);
-    for (uint32_t base = 0; base < nitems; base += kPrefetch * kThreads) {
-      uint4 pf[kPrefetch];
-#pragma unroll
-      for (int k = 0; k < kPrefetch; ++k) {
-        const uint32_t i = base + threadIdx.x + k * kThreads;
-        const uint4* src = i < nitems ? item_src(P, gi, i) : nullptr;
-        pf[k] = src ? *src : make_uint4(0, 0, 0, 0);
-      }
-#pragma clang loop unroll(full)
-      for (int k = 0; k < kPrefetch; ++k) {
-        const uint32_t i = base + threadIdx.x + k * kThreads;
-        if (i < nitems) crt_item_store<C>(P, K, gi, smem, i, pf[k]);
-      }
-    }
-    stage_zero_fill<C>(P, gi, smem);
-  }
-  __syncthreads();
-  const uint64_t unit = grp * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (unit >= total_units) return;
-  const uint64_t prod = unit >> P.log2U;
-  const uint32_t tile = (uint32_t)(unit & (U - 1));
-  const int zt = (int)(tile % P.tz), ut = (int)(tile / P.tz);
-  const uint8_t* slot = smem + (uint32_t)(prod - gi.first) * P.slot_bytes;
-  v16i acc[C];
-  crt_tile<C>(P, slot, slot + C * P.a_plane, 32 * zt, 32 * ut, gi.v_lo, acc);
-  uint32_t li;
-  const uint64_t gprod = global_product(P, prod, &li);
-  crt_epilogue<C>(P, K, gprod, li, 32 * zt, 32 * ut, acc);
 }
 
 }  // namespace pm

@@ -485,7 +485,7 @@ __device__ __forceinline__ void item_store(const Mfma32Params& P, const GroupInf
 // Parts of the staged B rows that no item writes but valid outputs read: bytes
 // w in [t, rowlen) of rows v < r (only when t < 32).  Rows v >= r feed only
 // discarded output columns; they are cleared too so LDS content is deterministic.
-template <int L>
+template <int L, int NT = kThreads>
 __device__ __forceinline__ void zero_fill_b(const Mfma32Params& P, uint8_t* bbase, int v_lo) {
   const int row_dw = (int)(P.rowlen >> 2);
   const int tq = (int)(P.t >> 2);
@@ -494,23 +494,23 @@ __device__ __forceinline__ void zero_fill_b(const Mfma32Params& P, uint8_t* bbas
     if (tq < row_dw) {
       const int pad = row_dw - tq;
       const int cnt = zr0 < (int)P.b_rows ? zr0 * pad : (int)P.b_rows * pad;
-      for (int e = threadIdx.x; e < cnt; e += kThreads) {
+      for (int e = threadIdx.x; e < cnt; e += NT) {
         const int row = e / pad, wd = tq + e % pad;
 #pragma unroll
         for (int i = 0; i < L; ++i) *(uint32_t*)(bbase + i * P.b_plane + row * P.b_rowstride + wd * 4) = 0u;
       }
     }
     const int nz = ((int)P.b_rows - zr0) * row_dw;
-    for (int e = threadIdx.x; e < nz; e += kThreads) {
+    for (int e = threadIdx.x; e < nz; e += NT) {
       const int row = zr0 + e / row_dw, wd = e % row_dw;
 #pragma unroll
       for (int i = 0; i < L; ++i) *(uint32_t*)(bbase + i * P.b_plane + row * P.b_rowstride + wd * 4) = 0u;
     }
   }
 }
-template <int L>
+template <int L, int NT = kThreads>
 __device__ __forceinline__ void stage_zero_fill(const Mfma32Params& P, const GroupInfo& gi, uint8_t* smem) {
-  for (uint32_t s = 0; s < gi.nslots; ++s) zero_fill_b<L>(P, smem + s * P.slot_bytes + L * P.a_plane, gi.v_lo);
+  for (uint32_t s = 0; s < gi.nslots; ++s) zero_fill_b<L, NT>(P, smem + s * P.slot_bytes + L * P.a_plane, gi.v_lo);
 }
 
 // Staging for n >= 256.  The group's items, in order (slot, then a's n/4 word

@@ -394,21 +394,36 @@ polymul_status fill_crt(CrtConsts& K, const uint32_t* qs, uint32_t lc, uint64_t 
     K.magic[c] = (uint32_t)((1ull << 32) / mc);
     K.off[c] = (uint32_t)((1ull << 31) % mc);
     K.invm[c] = 1.0f / (float)mc;
+    K.mf[c] = (float)mc;
+    K.r16[c] = (int32_t)((1u << 16) % mc);
     for (uint32_t i = 0; i < lc; ++i) K.w[i][c] = (uint32_t)(Mc % qs[i]);
   }
   for (uint32_t i = 0; i < lc; ++i) K.Mq[i] = (uint32_t)(M % qs[i]);
   return POLYMUL_OK;
 }
 
-template <int C, bool SMALL> const void* k_crt() { return (const void*)crt_group_kernel<C, SMALL>; }
+template <int C, bool SMALL, bool SHARE22> const void* k_crt() {
+  return (const void*)crt_wave_kernel<C, SMALL, SHARE22>;
+}
 
-template <int C, bool SMALL>
-polymul_status launch_crt_C(const Mfma32Params& P, const CrtConsts& K, uint32_t lds, hipStream_t s) {
-  if (allow_lds<k_crt<C, SMALL>>() != POLYMUL_OK) return POLYMUL_EDEVICE;
+template <int C, bool SMALL, bool SHARE22>
+polymul_status launch_crt_CS(const Mfma32Params& P, const CrtConsts& K, uint32_t lds, hipStream_t s) {
+  if (allow_lds<k_crt<C, SMALL, SHARE22>>() != POLYMUL_OK) return POLYMUL_EDEVICE;
   const uint64_t groups = ((P.nprod << P.log2U) + 3) / 4;
   if (groups > 0x7FFFFFFFull) return POLYMUL_EUNSUPPORTED;
-  hipLaunchKernelGGL((crt_group_kernel<C, SMALL>), dim3((uint32_t)groups), dim3(kThreads), lds, s, P, K);
+  hipLaunchKernelGGL((crt_wave_kernel<C, SMALL, SHARE22>), dim3((uint32_t)groups), dim3(CrtWaves<C>::kThreadsW),
+                     lds, s, P, K);
   return launch_status();
+}
+
+// Dynamic LDS: the residue planes, or the combine step's bytes laid over them if larger.
+template <int C, bool SMALL>
+polymul_status launch_crt_C(const Mfma32Params& P, const CrtConsts& K, uint32_t lds, hipStream_t s) {
+  lds = std::max(lds, crt_combine_bytes<C>());
+  if (lds > kMaxLds) return POLYMUL_EUNSUPPORTED;
+  // one product in 2 x 2 tiles per group: the four tiles share A by row and B by column
+  const bool share22 = !SMALL && P.log2U == 2 && P.tz == 2 && P.slots == 1;
+  return share22 ? launch_crt_CS<C, SMALL, true>(P, K, lds, s) : launch_crt_CS<C, SMALL, false>(P, K, lds, s);
 }
 
 // Channel counts with a kernel instance; a product needing fewer moduli takes
@@ -432,12 +447,17 @@ polymul_status run_crt(const uint32_t* a, const uint32_t* b, uint32_t* c, uint32
     if (K.C != want) return POLYMUL_EUNSUPPORTED;
   }
   const int C = (int)K.C;
-  // the largest tile side whose planes fit (fewest staged bytes)
+  // n = 4096: tile side 64, four tiles of one product in 2 x 2 (fragments shared);
+  // otherwise the largest tile side whose planes fit (fewest staged bytes)
   Mfma32Params P;
   uint32_t lds = 0;
   st = POLYMUL_EUNSUPPORTED;
+  if (n == 4096) {
+    st = fill_mfma32(P, a, b, c, n, qs, lc, nq_total, l0, nprod, 4, 64, &lds, false, 1, false, C);
+    if (st == POLYMUL_EINVAL) return st;
+  }
   const uint32_t t0 = n <= 32 ? n : std::min<uint32_t>(128, n);
-  for (uint32_t t = t0; t >= (n <= 32 ? n : 32u); t /= 2) {
+  for (uint32_t t = t0; st != POLYMUL_OK && t >= (n <= 32 ? n : 32u); t /= 2) {
     st = fill_mfma32(P, a, b, c, n, qs, lc, nq_total, l0, nprod, 4, t, &lds, false, 1, false, C);
     if (st == POLYMUL_EINVAL) return st;
     if (st == POLYMUL_OK) break;

@@ -1,7 +1,8 @@
 // Host check of the library's modular-arithmetic helpers against plain 128-bit
 // integer arithmetic: the Barrett reductions and balanced digit splits of the
-// 32-bit-modulus paths (pm_common.h) and the reciprocal 128/64 remainder and
-// per-modulus constants of the 64-bit paths (pm_wide.h, pm_wide_host.h).  These
+// 32-bit-modulus paths (pm_common.h), the centred small-modulus residues of the
+// CRT path (pm_common.h) and the reciprocal 128/64 remainder and per-modulus
+// constants of the 64-bit paths (pm_wide.h, pm_wide_host.h).  These
 // helpers are __host__ __device__, so the code the kernels run is the code
 // compiled here for the CPU.  Built by tests/test_host_arith.py (also under the
 // address and undefined-behaviour sanitizers); prints "ok <cases>" or the first
@@ -156,6 +157,37 @@ static void check_mod64(uint64_t q) {
           (unsigned long long)q);
 }
 
+// residue_centred: r = v (mod m) and r in [-128, 127] for every 32-bit v.
+static void check_residue8(uint32_t m) {
+  const int32_t r16 = (int32_t)((1u << 16) % m);
+  const float mf = (float)m, im = 1.0f / (float)m;
+  auto one = [&](int32_t v) {
+    const int32_t r = residue_centred(v, m, r16, mf, im);
+    int64_t d = ((int64_t)v - r) % (int64_t)m;
+    CHECK(d == 0 && r >= -128 && r <= 127, "residue_centred m=%u v=%d -> %d", m, v, r);
+  };
+  for (int32_t v = -(1 << 18); v <= (1 << 18); ++v) one(v);
+  for (int32_t hi = -32768; hi < 32768; hi += 1) {  // around every multiple of 2^16
+    one((int32_t)((uint32_t)hi << 16));
+    one((int32_t)((uint32_t)hi << 16) + 0xFFFF);
+    one((int32_t)((uint32_t)hi << 16) + (int32_t)(next64() & 0xFFFF));
+  }
+  const int32_t e[] = {INT32_MAX, INT32_MIN, INT32_MIN + 1, INT32_MAX - 1, (int32_t)0x7F7F7F7F, (int32_t)0x80808080};
+  for (int32_t v : e) one(v);
+  for (int i = 0; i < 200000; ++i) one((int32_t)next64());
+  // the fp32 step itself, exhaustively over every |x| < 2^23 + 2^16
+  if (m < 256) {
+    const int32_t xmax = (1 << 23) + (1 << 16);
+    for (int32_t x = -xmax + 1; x < xmax; ++x) {
+      const int32_t r = centred_mod_small(x, m, mf, im);
+      if (r < -128 || r > 127 || ((int64_t)x - r) % (int64_t)m != 0) {
+        CHECK(false, "centred_mod_small m=%u x=%d -> %d", m, x, r);
+      }
+    }
+    g_cases += 2u * (uint32_t)xmax - 1;
+  }
+}
+
 int main(int argc, char** argv) {
   if (argc > 1) g_state ^= strtoull(argv[1], nullptr, 10);
   const uint32_t q32[] = {2u, 3u, 17u, 251u, 256u, 257u, 3329u, 12289u, 65536u, 65537u, 1u << 24, (1u << 24) + 1,
@@ -173,6 +205,8 @@ int main(int argc, char** argv) {
     uint64_t q = next64() >> (next64() % 62);
     check_mod64(q < 2 ? 2 : q);
   }
+  const uint32_t m8[] = {256, 255, 253, 251, 247, 241, 239, 233, 229, 227, 223, 211, 199, 2, 3, 5, 7, 17, 127, 128, 254};
+  for (uint32_t m : m8) check_residue8(m);
   printf("ok %llu\n", g_cases);
   return 0;
 }

@@ -79,3 +79,52 @@ def test_planted_mistake_is_caught():
     wrong = [sum(((x % m) * pow(M // m % m, -1, m) % m) * (M // m) for m in ms) % q for x in X]
     want = oracle.negacyclic(a.astype(np.uint32)[None], b.astype(np.uint32)[None], q)[0]
     assert [int(x) for x in wrong] != [int(x) for x in want]
+
+
+def _f32_kappa_sum(s, ms):
+    """The kernels' fp32 evaluation of sum_c s_c / m_c + 0.5: terms fl(s_c * fl(1/m_c)),
+    added in channel order, then + 0.5."""
+    f = np.float32(0.0)
+    for sc, m in zip(s, ms):
+        f = np.float32(f + np.float32(np.float32(sc) * np.float32(np.float32(1.0) / np.float32(m))))
+    return np.float32(f + np.float32(0.5))
+
+
+@pytest.mark.parametrize("n,q", [(4096, 1068236801), (4096, (1 << 32) - 5), (1, (1 << 32) - 5), (256, 3329)])
+def test_kappa_fp32_sum_within_its_bound(n, q):
+    """The rounding count kappa = round(sum_c s_c / m_c) is taken from an fp32 sum.
+    Over sums X at and next to the extremes +-B (the largest centred negacyclic
+    sums, B = n floor(q/2)^2), X = 0 and random X, and over the residue vector
+    with every s_c = m_c - 1 (every term and running sum at its largest), the fp32
+    value stays within the stated bound (2C + C(C+1)/2 + C + 1) 2^-24 of the exact
+    fraction, that bound stays below the 2^-17 margin the moduli rule leaves, and
+    kappa comes out exact."""
+    from fractions import Fraction
+    ms = moduli(n, q)
+    C = len(ms)
+    M = math.prod(ms)
+    u = Fraction(1, 1 << 24)
+    bound = (2 * C + C * (C + 1) // 2 + C + 1) * u
+    assert bound < Fraction(1, 1 << 17)
+    B = n * (q // 2) ** 2
+    rng = np.random.Generator(np.random.PCG64(C))
+    xs = [B, -B, B - 1, -B + 1, 0, 1, -1] + [int(x) for x in rng.integers(-B, B, size=200, dtype=np.int64)] \
+        if B < (1 << 62) else [B, -B, 0, 1, -1]
+    worst = Fraction(0)
+    for X in xs:
+        s = [(X % m) * pow(M // m % m, -1, m) % m for m in ms]
+        exact = sum(Fraction(sc, m) for sc, m in zip(s, ms))  # = X / M + kappa
+        kappa = exact - Fraction(X, M)
+        assert kappa.denominator == 1
+        # the true fraction sits at least 2^-17 from the rounding boundary
+        assert abs(Fraction(X, M)) <= Fraction(1, 2) - Fraction(1, 1 << 17)
+        f = _f32_kappa_sum(s, ms)
+        err = abs(Fraction(float(f)) - (exact + Fraction(1, 2)))
+        worst = max(worst, err)
+        assert err <= bound, (X, float(err), float(bound))
+        assert math.floor(float(f)) == kappa
+    # every term at its largest: m_c - 1 (a residue vector, whatever X it stands for)
+    s = [m - 1 for m in ms]
+    exact = sum(Fraction(sc, m) for sc, m in zip(s, ms)) + Fraction(1, 2)
+    err = abs(Fraction(float(_f32_kappa_sum(s, ms))) - exact)
+    assert err <= bound
