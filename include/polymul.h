@@ -274,7 +274,7 @@ polymul_status polymul_tune_get(uint64_t n, uint32_t L, uint32_t* t);
  * Process-wide scheduling knobs of grouped plans (paper Sec. 2.6: parameters
  * found by experiment), read when a plan is created; results never depend on
  * them.  No HIP call is made.  EINVAL: unknown parameter or value out of range.
- *   POLYMUL_TUNE_PLAN_SHARE_PCT (10..1000, default 100): items estimated to take
+ *   POLYMUL_TUNE_PLAN_SHARE_PCT (10..1000, default 140): items estimated to take
  *     longer than this percentage of a CU's even share of the plan's work have
  *     their K range cut into runs.
  *   POLYMUL_TUNE_PLAN_STREAM_PCT (50..400, default 125): weight of a K-streamed

@@ -783,7 +783,7 @@ void plan_free(polymul_plan* p) {
 // of a CU's even share of the plan's work, and the weight of a streamed block's MFMA
 // work relative to a resident group's (its chunked staging and 128-bit flushes make
 // it slower than its MFMA count says), as a percentage.
-std::atomic<uint32_t> g_plan_share_pct{100};
+std::atomic<uint32_t> g_plan_share_pct{140};
 std::atomic<uint32_t> g_plan_stream_pct{125};
 
 // Estimated time of one item (MFMAs per wave of its four tiles, the streamed

@@ -257,7 +257,7 @@ def test_karatsuba_u64_arguments():
 
 
 def test_plan_tuning_knobs():
-    assert pm.polymul_tune_param_get("plan_share_pct") == 100
+    assert pm.polymul_tune_param_get("plan_share_pct") == 140
     assert pm.polymul_tune_param_get("plan_stream_pct") == 125
     lib = pm.load_library()
     assert lib.polymul_tune_param_set(1, 9) == EINVAL
@@ -269,7 +269,7 @@ def test_plan_tuning_knobs():
     assert lib.polymul_tune_param_set(3, 3) == EINVAL
     pm.polymul_tune_param_set("plan_share_pct", 250)
     assert pm.polymul_tune_param_get("plan_share_pct") == 250
-    pm.polymul_tune_param_set("plan_share_pct", 100)
+    pm.polymul_tune_param_set("plan_share_pct", 140)
 
 
 def test_karatsuba_depth_table():

@@ -179,7 +179,7 @@ def test_plan_small_moduli_limb_counts():
         try:
             plan = pm.Plan(groups)
         finally:
-            pm.polymul_tune_param_set("plan_share_pct", 100)
+            pm.polymul_tune_param_set("plan_share_pct", 140)
             pm.polymul_tune_param_set("plan_stream_pct", 125)
         for rep in range(2):
             for g in groups:

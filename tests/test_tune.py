@@ -20,7 +20,7 @@ def _cache(**kw):
            "tiles": [{"n": 2048, "L": 4, "t": 128}],
            "karatsuba": [{"n": 4096, "products": 2048, "depth": 3}],
            "karatsuba64": [{"n": 65536, "products": 16, "depth": 2}],
-           "params": {"plan_share_pct": 140, "plan_stream_pct": 150, "u64_karatsuba_runs": 2}}
+           "params": {"plan_share_pct": 160, "plan_stream_pct": 150, "u64_karatsuba_runs": 2}}
     rec.update(kw)
     return json.dumps(rec)
 
@@ -29,7 +29,7 @@ def _reset():
     pm.polymul_tune_set(2048, 4, 0)
     pm.polymul_tune_set_karatsuba(4096, 2048, 4, pm.binding.KARATSUBA_BUILTIN)
     pm.polymul_tune_set_karatsuba(65536, 16, 8, pm.binding.KARATSUBA_BUILTIN)
-    pm.polymul_tune_param_set("plan_share_pct", 100)
+    pm.polymul_tune_param_set("plan_share_pct", 140)
     pm.polymul_tune_param_set("plan_stream_pct", 125)
     pm.polymul_tune_param_set("u64_karatsuba_runs", 4)
 
@@ -47,7 +47,7 @@ def test_corrupt_stale_or_foreign_cache_is_ignored(tmp_path, monkeypatch):
     assert tune.apply(str(p)) is False
     assert pm.polymul_tune_get(2048, 4) == 64
     assert pm.polymul_tune_get_karatsuba(4096, 2048, 4) == 2
-    assert pm.polymul_tune_param_get("plan_share_pct") == 100
+    assert pm.polymul_tune_param_get("plan_share_pct") == 140
     p.write_text(_cache(tiles=[{"n": 4096, "L": 4, "t": 48}]))
     try:
         assert tune.apply(str(p)) is False
@@ -66,7 +66,7 @@ def test_cache_is_applied(tmp_path, monkeypatch):
         assert pm.polymul_tune_get(2048, 4) == 128
         assert pm.polymul_tune_get_karatsuba(4096, 2048, 4) == 3
         assert pm.polymul_tune_get_karatsuba(65536, 16, 8) == 2
-        assert pm.polymul_tune_param_get("plan_share_pct") == 140
+        assert pm.polymul_tune_param_get("plan_share_pct") == 160
         assert pm.polymul_tune_param_get("plan_stream_pct") == 150
         assert pm.polymul_tune_param_get("u64_karatsuba_runs") == 2
     finally:
