@@ -323,7 +323,9 @@ def main():
         "shared_operand": shared,
         "rns_crt": crt,
         "plain_int": {"value": plain_value, "unit": "polymuls/s", "ms_per_step": ms_plain,
-                      "mfma_speedup": value / plain_value},
+                      "mfma_speedup": value / plain_value,
+                      "tmac_per_s": products * n * n / (ms_plain / 1e3) / 1e12,
+                      "kernel": "plain_kernel (v_mad_u64_u32 per 32x32-bit term, lazy folds)"},
     }
     out["parity"] = None
     if not args.no_cpu_baseline:

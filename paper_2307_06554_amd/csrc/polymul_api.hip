@@ -872,6 +872,13 @@ polymul_status polymul_negacyclic_plain(const uint32_t* a, const uint32_t* b, ui
   P.a = a; P.b = b; P.c = c; P.batch = batch; P.n = (uint32_t)n;
   P.blocks_per_prod = (uint32_t)((n + kPlainOut - 1) / kPlainOut);
   P.m = make_mod32(q, 4);
+  // lazy sums: after a fold s <= (2^32 - 1)(R + 1) with R = 2^32 mod q, and
+  // F = floor((2^64 - 1 - that) / (q - 1)^2) >= 1 more products fit
+  P.r32 = (uint32_t)((1ull << 32) % q);
+  const uint64_t smax = 0xFFFFFFFFull * ((uint64_t)P.r32 + 1);
+  const uint64_t qm1 = q - 1;
+  const uint64_t F = (UINT64_MAX - smax) / (qm1 * qm1);
+  P.fold_bodies = F >= 16 ? (uint32_t)std::min<uint64_t>(F / 16, 1u << 20) : 0u;
   const uint64_t blocks = batch * P.blocks_per_prod;
   if (blocks > 0x7FFFFFFFull) return POLYMUL_EUNSUPPORTED;
   hipLaunchKernelGGL(plain_kernel, dim3((uint32_t)blocks), dim3(kPlainThreads), 0, stream, P);

@@ -119,6 +119,21 @@ def test_plain_kernel(n, q):
     _check(pm.polymul_negacyclic_plain, _rand(rng, (3, n), q), _rand(rng, (3, n), q), q)
 
 
+@pytest.mark.parametrize("q", [2, 3329, Q30, (1 << 31) - 1, (1 << 31) + 6, 2863311531, (1 << 32) - 5])
+def test_plain_kernel_largest_terms(q):
+    """Every term of the middle outputs is (q - 1)^2, the most a lazy sum takes
+    between folds (b_k = q - 1 below n/2 and 1 above, so the wrapped operand
+    q - b_(n+k) is q - 1 too), words above q, and degrees of several input chunks."""
+    n = 4096
+    a = np.full((2, n), q - 1, dtype=np.uint32)
+    b = np.where(np.arange(n) < n // 2, q - 1, 1).astype(np.uint32)[None, :].repeat(2, axis=0)
+    a[1, ::3] = np.uint32(0xFFFFFFFF)
+    _check(pm.polymul_negacyclic_plain, a, b, q)
+    rng = np.random.Generator(np.random.PCG64(q % 1000))
+    for n in (8192, 16384):
+        _check(pm.polymul_negacyclic_plain, _rand(rng, (2, n), q), _rand(rng, (2, n), q), q)
+
+
 def test_rns_channels():
     w = inputs.make_workload(2, scale=3 / 256)
     got = to_host(pm.polymul_negacyclic_rns(to_dev(w.a), to_dev(w.b), w.qs), np.uint32)
