@@ -256,18 +256,13 @@ __device__ __forceinline__ uint64_t flush_value(const v16i (&acc)[2 * L - 1], in
   }
   return submod64(mod_u128(x.hi, x.lo, m), m.foff, m.q);
 }
-// Residues in registers (res) or, for L = 8, in LDS (resl: word rr of thread i at rr * 256 + i).
-template <int L, typename W, int N>
-__device__ __forceinline__ void stream_flush(v16i (&acc)[2 * L - 1], W (&res)[N], W* resl, const ModQ64& m) {
+// Running residues in registers (up to four limbs; eight limbs: stream8_block).
+template <int L, typename W>
+__device__ __forceinline__ void stream_flush(v16i (&acc)[2 * L - 1], W (&res)[16], const ModQ64& m) {
 #pragma unroll
   for (int rr = 0; rr < 16; ++rr) {
     const uint64_t v = flush_value<L>(acc, rr, m);
-    if constexpr (L == 8) {
-      W& r = resl[rr * kStreamThreads + threadIdx.x];
-      r = (W)addmod64((uint64_t)r, v, m.q);
-    } else {
-      res[rr] = (W)addmod64((uint64_t)res[rr], v, m.q);
-    }
+    res[rr] = (W)addmod64((uint64_t)res[rr], v, m.q);
     __builtin_amdgcn_sched_barrier(0);
   }
 #pragma unroll
@@ -278,6 +273,7 @@ __device__ __forceinline__ void stream_flush(v16i (&acc)[2 * L - 1], W (&res)[N]
 // wg = product * ublocks + u-block.
 template <int L, typename W>
 __device__ __forceinline__ void stream_block(const StreamParams& P, uint64_t item, uint8_t* smem) {
+  static_assert(L <= 4, "eight limbs run stream8_block");
   const uint64_t wg = item / P.kparts;  // block (product, u-block)
   const uint32_t part = (uint32_t)(item - wg * P.kparts);
   const int cpp = (int)(P.nchunks / P.kparts);
@@ -316,14 +312,9 @@ __device__ __forceinline__ void stream_block(const StreamParams& P, uint64_t ite
   v16i acc[2 * L - 1];
 #pragma unroll
   for (int s = 0; s < 2 * L - 1; ++s) acc[s] = v16i{};
-  // running residues: registers, or LDS for L = 8 (one wave per SIMD and every register taken)
-  W res[L == 8 ? 1 : 16];
-  W* resl = (W*)(smem + P.lds_res);
+  W res[16];  // running residues of the lane's 16 outputs
 #pragma unroll
-  for (int rr = 0; rr < 16; ++rr) {
-    if constexpr (L == 8) resl[rr * kStreamThreads + threadIdx.x] = 0;
-    else res[rr] = 0;
-  }
+  for (int rr = 0; rr < 16; ++rr) res[rr] = 0;
 
   // per-lane A base: S = S_base + (dc - 1 - dl) t + w0 inside the chunk's window
   const int S_base = 32 * (int)P.tz - 1 - z0 - zl + 16 * g;
@@ -375,7 +366,7 @@ __device__ __forceinline__ void stream_block(const StreamParams& P, uint64_t ite
         mfma_step_tail<L>(acc, af, araw, (uint32_t)(S_of(sn) & 3), abuf, P.a_win, S_of(s2), b, ring,
                           kRing * P.rs, B_of(sn));
       }
-      if (!more || (c + 1 - c0) % (int)P.flush_every == 0) stream_flush<L, W>(acc, res, resl, m);
+      if (!more || (c + 1 - c0) % (int)P.flush_every == 0) stream_flush<L, W>(acc, res, m);
     }
     if (!more) break;
     // ---- convert and write the next chunk (its A buffer and ring rows are not read now)
@@ -407,11 +398,239 @@ __device__ __forceinline__ void stream_block(const StreamParams& P, uint64_t ite
 #pragma unroll
   for (int rr = 0; rr < 16; ++rr) {
     const int z = z0 + 8 * (rr >> 2) + 4 * g + (rr & 3);
-    if (z < t) {
-      if constexpr (L == 8) C[(size_t)u * t + z] = resl[rr * kStreamThreads + threadIdx.x];
-      else C[(size_t)u * t + z] = res[rr];
+    if (z < t) C[(size_t)u * t + z] = res[rr];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Eight limbs (64-bit words): the 15 shift classes s = i + j split by parity over
+// a pair of waves, so that a wave holds 8 (even s) or 7 (odd s) accumulator sets
+// instead of 15 and two waves fit on a SIMD.  512 threads: wave w computes tile
+// (zt, ut) = (w & 1, (w >> 1) & 1) of the 64 x 64 block for the classes of parity
+// par = w >> 2, i.e. the limb pairs (i, j) with i + j = par (mod 2), 32 of the 64.
+// Both waves of a pair read the same staged runs; each flushes its own classes'
+// part sum_s T_s 2^(8s) into the pair's running residues in LDS, the two at
+// different chunks (so the updates never overlap) and the last after a barrier.
+// ---------------------------------------------------------------------------
+constexpr int kStream8Threads = 512;
+
+template <int PAR>
+__device__ __forceinline__ uint64_t flush_value_par(const v16i (&acc)[8], int rr, const ModQ64& m) {
+  U128 x{0, 0};
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    int64_t y = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int sc = 4 * j + k;
+      if (sc < 15 && (sc & 1) == PAR) y += (int64_t)acc[sc >> 1][rr] * ((int64_t)1 << (8 * k));
+    }
+    const uint64_t yo = (uint64_t)y + ((uint64_t)1 << 56);  // in (0, 2^57), as in flush_value
+    x = add128(x, j == 0 ? U128{yo, 0} : mul64x64(yo, m.r[4 * j]));
+  }
+  return submod64(mod_u128(x.hi, x.lo, m), m.foff, m.q);
+}
+
+template <int PAR, typename W>
+__device__ __forceinline__ void stream_flush_par(v16i (&acc)[8], W* resl, const ModQ64& m) {
+  const uint32_t tid = threadIdx.x & (kStreamThreads - 1);
+#pragma unroll
+  for (int rr = 0; rr < 16; ++rr) {
+    const uint64_t v = flush_value_par<PAR>(acc, rr, m);
+    W& r = resl[rr * kStreamThreads + tid];
+    r = (W)addmod64((uint64_t)r, v, m.q);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+#pragma unroll
+  for (int s = 0; s < 8; ++s) acc[s] = v16i{};
+}
+
+__device__ __forceinline__ v4i align_run(const uint32_t (&x)[5], uint32_t sh) {
+  v4i a;
+  a[0] = (int)__builtin_amdgcn_alignbyte(x[1], x[0], sh);
+  a[1] = (int)__builtin_amdgcn_alignbyte(x[2], x[1], sh);
+  a[2] = (int)__builtin_amdgcn_alignbyte(x[3], x[2], sh);
+  a[3] = (int)__builtin_amdgcn_alignbyte(x[4], x[3], sh);
+  return a;
+}
+__device__ __forceinline__ void load_run(uint32_t (&x)[5], const uint8_t* plane, int S) {
+  const uint32_t* p = (const uint32_t*)plane + (S >> 2);
+#pragma unroll
+  for (int k = 0; k < 5; ++k) x[k] = p[k];
+}
+
+// One K-step of the parity-PAR classes.  On entry a holds limb 0's aligned A run
+// of this step, x[0] and x[1] the raw runs of limbs 1 and 2, b all eight B runs.
+// A limbs are taken one at a time, their runs read two limbs ahead (limb k of
+// the next step counted as limb 8 + k); the B runs of the next step are read
+// once the last limb that uses them has issued (limb 6 for j = PAR mod 2, limb 7
+// for the others).  On exit the registers hold the next step's entry state.
+template <int PAR>
+__device__ __forceinline__ void mfma_step_par(v16i (&acc)[8], v4i& a, uint32_t (&x)[2][5], v4i (&b)[8],
+                                              const uint8_t* abuf, uint32_t a_win, int S, int S_next,
+                                              const uint8_t* ring, uint32_t b_plane, int boff_next) {
+  const uint32_t sh = (uint32_t)(S & 3), sh_next = (uint32_t)(S_next & 3);
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+#pragma unroll
+    for (int j = (PAR + i) & 1; j < 8; j += 2)
+      acc[(i + j) >> 1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b[j], acc[(i + j) >> 1], 0, 0, 0);
+    a = align_run(x[i & 1], i + 1 < 8 ? sh : sh_next);  // limb i + 1
+    const int k = i + 3;                                 // the limb whose runs are read now
+    load_run(x[i & 1], abuf + (k & 7) * a_win, k < 8 ? S : S_next);
+    if (i == 6) {
+#pragma unroll
+      for (int j = PAR; j < 8; j += 2) b[j] = *(const v4i*)(ring + j * b_plane + boff_next);
+    } else if (i == 7) {
+#pragma unroll
+      for (int j = 1 - PAR; j < 8; j += 2) b[j] = *(const v4i*)(ring + j * b_plane + boff_next);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// The K loop of one chunk for this wave's parity.
+template <int PAR>
+__device__ __forceinline__ void chunk_mfma_par(v16i (&acc)[8], const uint8_t* abuf, uint32_t a_win,
+                                               const uint8_t* ring, uint32_t b_plane, int S_base, int dc, int t,
+                                               int spd, uint32_t log2spd, int D0, int u0, int zl, int g, int rs,
+                                               int steps) {
+  auto S_of = [&](int st) { return S_base + (dc - 1 - (st >> log2spd)) * t + ((st & (spd - 1)) << 5); };
+  auto B_of = [&](int st) {
+    const int d = D0 + (st >> log2spd);
+    return ((u0 + zl - d) & (kRing - 1)) * rs + ((st & (spd - 1)) << 5) + 16 * g;
+  };
+  v4i b[8];
+  const int B0 = B_of(0);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) b[j] = *(const v4i*)(ring + j * b_plane + B0);
+  uint32_t x[2][5];
+  const int S0 = S_of(0);
+  load_run(x[0], abuf, S0);
+  v4i a = align_run(x[0], (uint32_t)(S0 & 3));
+  load_run(x[0], abuf + a_win, S0);
+  load_run(x[1], abuf + 2 * a_win, S0);
+  for (int st = 0; st < steps; ++st) {
+    const int sn = st + 1 < steps ? st + 1 : st;  // the last step re-reads its own runs
+    mfma_step_par<PAR>(acc, a, x, b, abuf, a_win, S_of(st), S_of(sn), ring, b_plane, B_of(sn));
+  }
+}
+
+template <int PAR, typename W>
+__device__ __forceinline__ void stream8_block(const StreamParams& P, uint64_t item, uint8_t* smem) {
+  const uint64_t wg = item / P.kparts;  // block (product, u-block)
+  const uint32_t part = (uint32_t)(item - wg * P.kparts);
+  const int cpp = (int)(P.nchunks / P.kparts);
+  const int c0 = (int)part * cpp, c1 = c0 + cpp;
+  const uint64_t prod = wg / P.ublocks;
+  const int U0 = 64 * (int)(wg - prod * P.ublocks);
+  const uint32_t li = P.lrep > 1 ? (uint32_t)((prod / P.lrep) % P.lc) : (uint32_t)(prod % P.lc);
+  const uint64_t gp = P.lrep > 1 ? prod : (prod / P.lc) * P.nq_total + P.l0 + li;
+  const uint64_t bgp = P.b_shared ? (uint64_t)(P.l0 + li) : gp;
+  const ModQ64& m = P.mods[li];
+  uint8_t* ring = smem + P.lds_b;
+  const uint32_t tid = threadIdx.x & (kStreamThreads - 1);  // position in the wave pair's tile
+  const int wave = (int)(tid >> 6);
+  const int lane = (int)(tid & 63);
+  const int zt = wave & 1, ut = wave >> 1;
+  const bool active = zt < (int)P.tz;
+  const int z0 = 32 * zt, u0 = U0 + 32 * ut;
+  const int zl = lane & 31, g = lane >> 5;
+  const int t = (int)P.t, rs = (int)P.rs;
+  const uint32_t b_plane = kRing * P.rs;
+
+  // ---- first chunk, loaded synchronously by all 512 threads
+  {
+    const ChunkItems ci = chunk_items(P, c0, U0, true);
+    const int I1 = (c0 * (int)P.dc + (int)P.dc - 1) * t + 32 * (int)P.tz - 1;
+    uint8_t* abuf0 = smem + (c0 & 1) * (8 * P.a_win);
+    for (int i = threadIdx.x; i < ci.count(); i += kStream8Threads) {
+      const StreamItem it = ci.item(i);
+      bool neg;
+      const W* src = item_ptr<W>(P, it, gp, bgp, &neg);
+      Quad<W> x{};
+      if (src) x = load_quad<W>(src);
+      item_write<8, W>(P, it, x, src != nullptr, neg, gp, bgp, m, abuf0, ring, I1);
     }
   }
+  // running residues of the pair's outputs in LDS, zeroed by the even-class wave
+  W* resl = (W*)(smem + P.lds_res);
+  if (PAR == 0) {
+#pragma unroll
+    for (int rr = 0; rr < 16; ++rr) resl[rr * kStreamThreads + tid] = 0;
+  }
+  __syncthreads();
+
+  v16i acc[8];
+#pragma unroll
+  for (int s = 0; s < 8; ++s) acc[s] = v16i{};
+  const int S_base = 32 * (int)P.tz - 1 - z0 - zl + 16 * g;
+  const int steps = (int)(P.dc << P.log2spd);
+  const int fe = (int)P.flush_every;  // >= 15 for eight limbs
+  for (int c = c0; c < c1; ++c) {
+    const bool more = c + 1 < c1;
+    if (active) {
+      const uint8_t* abuf = smem + (c & 1) * (8 * P.a_win);
+      chunk_mfma_par<PAR>(acc, abuf, P.a_win, ring, b_plane, S_base, (int)P.dc, t, (int)P.spd, P.log2spd,
+                          c * (int)P.dc, u0, zl, g, rs, steps);
+      // even classes flush every fe chunks, odd ones half a period later; the last
+      // chunk's even flush is here, its odd flush after the loop
+      const int done = c + 1 - c0;
+      if (more ? (done + PAR * (fe / 2)) % fe == 0 : PAR == 0) stream_flush_par<PAR, W>(acc, resl, m);
+    }
+    if (!more) break;
+    // The even-class waves, which the MFMA arbitration serves first, stage the next
+    // chunk (its A buffer and ring rows are not read by this chunk) while the
+    // odd-class waves are still in their K loop.
+    if (PAR == 0) {
+      const ChunkItems cn = chunk_items(P, c + 1, U0, false);
+      uint8_t* abuf_n = smem + ((c + 1) & 1) * (8 * P.a_win);
+      const int I1n = ((c + 1) * (int)P.dc + (int)P.dc - 1) * t + 32 * (int)P.tz - 1;
+      constexpr int kPf = 3;  // loads in flight per thread (a chunk has at most 3 * 256 items for t <= 64)
+      for (int base = 0; base < cn.count(); base += kPf * kStreamThreads) {
+        Quad<W> pf[kPf];
+        bool pl[kPf], pn[kPf];
+#pragma unroll
+        for (int k = 0; k < kPf; ++k) {
+          const int i = base + (int)tid + k * kStreamThreads;
+          pl[k] = false;
+          pn[k] = false;
+          if (i < cn.count()) {
+            const W* src = item_ptr<W>(P, cn.item(i), gp, bgp, &pn[k]);
+            if (src) { pf[k] = load_quad<W>(src); pl[k] = true; }
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < kPf; ++k) {
+          const int i = base + (int)tid + k * kStreamThreads;
+          if (i < cn.count()) item_write<8, W>(P, cn.item(i), pf[k], pl[k], pn[k], gp, bgp, m, abuf_n, ring, I1n);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  __syncthreads();  // the even flush of the last chunk is in LDS
+  if (PAR == 1 && active) stream_flush_par<1, W>(acc, resl, m);
+  __syncthreads();  // both halves of every residue are in
+  if (PAR == 1 || !active) return;
+
+  // ---- store the residues: lane holds z = z0 + 8 blk + 4 g + e, u = u0 + zl
+  const int u = u0 + zl;
+  if (u >= (int)P.r) return;
+  W* C = (P.kparts > 1 ? (W*)P.part_ws + (uint64_t)part * P.nprod * P.n : (W*)P.c) + gp * P.n;
+#pragma unroll
+  for (int rr = 0; rr < 16; ++rr) {
+    const int z = z0 + 8 * (rr >> 2) + 4 * g + (rr & 3);
+    if (z < t) C[(size_t)u * t + z] = resl[rr * kStreamThreads + tid];
+  }
+}
+
+template <typename W>
+__global__ __launch_bounds__(kStream8Threads) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void stream8_kernel(const StreamParams P) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  if (threadIdx.x < kStreamThreads) stream8_block<0, W>(P, blockIdx.x, smem);
+  else stream8_block<1, W>(P, blockIdx.x, smem);
 }
 
 template <int L, typename W, int WPE>

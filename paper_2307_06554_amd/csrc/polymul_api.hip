@@ -278,6 +278,7 @@ polymul_status allow_lds() {
 }
 template <int L, bool SMALL> const void* k_group() { return (const void*)mfma32_group_kernel<L, SMALL>; }
 template <int L, typename W, int WPE> const void* k_stream() { return (const void*)stream_kernel<L, W, WPE>; }
+template <typename W> const void* k_stream8() { return (const void*)stream8_kernel<W>; }
 const void* k_grouped() { return (const void*)grouped_kernel; }
 template <int L> const void* k_shared() { return (const void*)mfma32_shared_kernel<L>; }
 template <int L> const void* k_small() { return (const void*)mfma16_group_kernel<L>; }
@@ -518,10 +519,15 @@ polymul_status fill_stream(StreamParams& P, const void* a, const void* b, void* 
 
 template <int L, typename W, int WPE>
 polymul_status launch_stream_L(const StreamParams& P, uint32_t lds, hipStream_t s) {
-  if (allow_lds<k_stream<L, W, WPE>>() != POLYMUL_OK) return POLYMUL_EDEVICE;
   const uint64_t blocks = P.nprod * P.ublocks * P.kparts;
   if (blocks > 0x7FFFFFFFull) return POLYMUL_EUNSUPPORTED;
-  hipLaunchKernelGGL((stream_kernel<L, W, WPE>), dim3((uint32_t)blocks), dim3(kStreamThreads), lds, s, P);
+  if constexpr (L == 8) {  // shift classes split by parity over wave pairs
+    if (allow_lds<k_stream8<W>>() != POLYMUL_OK) return POLYMUL_EDEVICE;
+    hipLaunchKernelGGL((stream8_kernel<W>), dim3((uint32_t)blocks), dim3(kStream8Threads), lds, s, P);
+  } else {
+    if (allow_lds<k_stream<L, W, WPE>>() != POLYMUL_OK) return POLYMUL_EDEVICE;
+    hipLaunchKernelGGL((stream_kernel<L, W, WPE>), dim3((uint32_t)blocks), dim3(kStreamThreads), lds, s, P);
+  }
   return launch_status();
 }
 
@@ -537,7 +543,8 @@ polymul_status run_stream(const W* a, const W* b, W* c, uint32_t n, const uint64
   polymul_status st = fill_stream(P, a, b, c, n, qs, lc, nq_total, l0, nprod, L, &lds, cyclic, lrep, b_shared);
   if (st != POLYMUL_OK) return st;
   if (L == 4) return launch_stream_L<4, W, 2>(P, lds, s);
-  return launch_stream_L<8, W, 1>(P, lds, s);
+  if constexpr (sizeof(W) == 8) return launch_stream_L<8, W, 1>(P, lds, s);
+  return POLYMUL_EINVAL;
 }
 
 // nprod products (i -> global (i/lc)*nq_total + l0 + i%lc) with moduli qs[0..lc <= kMaxQ).
@@ -741,7 +748,7 @@ namespace {
 polymul_status plan_attrs() {
   if (allow_lds<k_grouped>() != POLYMUL_OK) return POLYMUL_EDEVICE;
   if (allow_lds<k_stream<4, uint64_t, 2>>() != POLYMUL_OK) return POLYMUL_EDEVICE;
-  if (allow_lds<k_stream<8, uint64_t, 1>>() != POLYMUL_OK) return POLYMUL_EDEVICE;
+  if (allow_lds<k_stream8<uint64_t>>() != POLYMUL_OK) return POLYMUL_EDEVICE;
   return POLYMUL_OK;
 }
 
