@@ -13,7 +13,10 @@ experiments are automated and their winners loaded into the library:
     polymul_tune_param_set.
 
 Every candidate is timed on the GPU on a batch large enough to fill it, best of
-three runs after the shader clock has settled.  Results go to a JSON cache keyed
+three runs after the shader clock has settled; a candidate replaces the built-in
+choice only if it is more than MARGIN faster (closer timings are noise, and a
+cache that flips between equals would move every figure taken with it).  Results
+go to a JSON cache keyed
 by the GPU architecture and by a hash of the kernel sources: a cache taken on
 other sources or another GPU is ignored, and the built-in choices stay.
 
@@ -31,6 +34,7 @@ from . import binding
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_CACHE = os.path.join(HERE, "tune_cache.json")
 CACHE_VERSION = 2
+MARGIN = 0.01
 Q30 = 1068236801
 GOLDILOCKS = (1 << 64) - (1 << 32) + 1
 
@@ -43,6 +47,14 @@ def csrc_hash():
         with open(os.path.join(d, name), "rb") as f:
             h.update(name.encode() + f.read())
     return h.hexdigest()[:16]
+
+
+def pick(timings, default, margin=MARGIN):
+    """The fastest key of `timings`, or `default` unless that is beaten by more than `margin`."""
+    best = min(timings, key=timings.get)
+    if default in timings and timings[best] > timings[default] * (1.0 - margin):
+        return default
+    return best
 
 
 def candidates(n):
@@ -107,7 +119,7 @@ def tune_tiles(ns, Ls, work, log):
                     binding.polymul_tune_set(n, L, 0)
             if not timings:
                 continue
-            best = min(timings, key=timings.get)
+            best = pick(timings, binding.polymul_tune_get(n, L))
             log(f"tile n={n:6d} L={L} products={products:6d} " +
                 " ".join(f"t={t}:{us:8.1f}us" for t, us in timings.items()) + f"  -> t={best}")
             entries.append({"n": n, "L": L, "t": best, "products": products,
@@ -132,7 +144,8 @@ def tune_karatsuba(shapes, log):
                              device="cuda")
             timings[d] = time_us(lambda: binding.polymul_negacyclic_rns_karatsuba(a, b, qs, d, workspace=ws, out=c))
             del ws
-        best = min(timings, key=timings.get)
+        binding.polymul_tune_set_karatsuba(n, batch * L, 4, binding.KARATSUBA_BUILTIN)
+        best = pick(timings, binding.polymul_tune_get_karatsuba(n, batch * L, 4))
         log(f"karatsuba n={n:6d} products={batch * L:6d} " +
             " ".join(f"d={d}:{us:8.1f}us" for d, us in timings.items()) + f"  -> depth {best}")
         entries.append({"n": n, "products": batch * L, "depth": best,
@@ -161,7 +174,9 @@ def tune_karatsuba64(shapes, log):
                     reps=4, trials=2)
             del ws
         binding.polymul_tune_param_set("u64_karatsuba_runs", 4)
-        key = min(timings, key=timings.get)
+        binding.polymul_tune_set_karatsuba(n, batch, 8, binding.KARATSUBA_BUILTIN)
+        d0 = binding.polymul_tune_get_karatsuba(n, batch, 8)
+        key = pick(timings, "0" if d0 == 0 else f"{d0}/4")
         depth, runs = (0, 4) if key == "0" else (int(key.split("/")[0]), int(key.split("/")[1]))
         log(f"karatsuba64 n={n:6d} products={batch:4d} " +
             " ".join(f"{k}:{us:8.1f}us" for k, us in timings.items()) + f"  -> depth {depth}, runs {runs}")
@@ -187,7 +202,7 @@ def tune_plan(log):
             plan = binding.Plan(groups)
             timings[f"{share}/{stream}"] = time_us(plan.execute, reps=50)
             plan.close()
-    key = min(timings, key=timings.get)
+    key = pick(timings, "140/125")
     share, stream = (int(x) for x in key.split("/"))
     binding.polymul_tune_param_set("plan_share_pct", share)
     binding.polymul_tune_param_set("plan_stream_pct", stream)

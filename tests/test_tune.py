@@ -72,3 +72,11 @@ def test_cache_is_applied(tmp_path, monkeypatch):
     finally:
         _reset()
 
+
+
+def test_pick_keeps_the_builtin_choice_within_the_margin():
+    assert tune.pick({32: 100.0, 64: 99.5, 128: 101.0}, 64) == 64
+    assert tune.pick({32: 99.5, 64: 100.0}, 64) == 64        # 0.5% faster: noise
+    assert tune.pick({32: 98.0, 64: 100.0}, 64) == 32        # 2% faster
+    assert tune.pick({"0": 50.0, "3/4": 40.0, "3/2": 39.9}, "3/4") == "3/4"
+    assert tune.pick({16: 80.0, 32: 100.0}, 48) == 16         # default not measured: the fastest
