@@ -80,9 +80,10 @@ __device__ __forceinline__ int32_t centred_lift(uint32_t x, uint32_t q) {
 // live while every item's four residues are formed and stored.
 constexpr int kStageItems = 4;
 
-template <int C, int NT>
+// CP channels from c0 into planes 0..CP-1 of slots laid out for CL planes (CL >= CP).
+template <int CP, int NT, int CL = CP>
 __device__ __forceinline__ void crt_stage_pass(const Mfma32Params& P, const CrtConsts& K, const GroupInfo& gi,
-                                               uint8_t* smem, uint32_t base, uint32_t nitems) {
+                                               uint8_t* smem, uint32_t base, uint32_t nitems, int c0 = 0) {
   const uint32_t lper = P.log2n - 1, quarter = P.n >> 2;
   uint4 pf[kStageItems];
 #pragma unroll
@@ -124,7 +125,7 @@ __device__ __forceinline__ void crt_stage_pass(const Mfma32Params& P, const CrtC
       v[k][1] = centred_lift(reduce_u32(x.y, m), m.q);
       v[k][2] = centred_lift(reduce_u32(x.z, m), m.q);
       v[k][3] = centred_lift(reduce_u32(x.w, m), m.q);
-      const uint32_t bbase = slot + C * P.a_plane;
+      const uint32_t bbase = slot + CL * P.a_plane;
       const int rp = vs - gi.v_lo, rn = vs - (int)P.r - gi.v_lo;
       dst1[k] = bbase + (uint32_t)(rp * (int)P.b_rowstride + wd * 4);
       dst2[k] = bbase + (uint32_t)(rn * (int)P.b_rowstride + wd * 4);
@@ -133,10 +134,10 @@ __device__ __forceinline__ void crt_stage_pass(const Mfma32Params& P, const CrtC
     }
   }
 #pragma unroll 1
-  for (int c = 0; c < C; ++c) {
-    const uint32_t m = K.m[c];
-    const int32_t r16 = K.r16[c];
-    const float mf = K.mf[c], im = K.invm[c];
+  for (int c = 0; c < CP; ++c) {
+    const uint32_t m = K.m[c0 + c];
+    const int32_t r16 = K.r16[c0 + c];
+    const float mf = K.mf[c0 + c], im = K.invm[c0 + c];
 #pragma unroll
     for (int k = 0; k < kStageItems; ++k) {
       if (!flags[k]) continue;
@@ -419,6 +420,160 @@ void crt_wave_kernel(const Mfma32Params P, const CrtConsts K) {
     uint32_t sw[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) sw[c] = sb[((c * 4 + i) * 4 + blk) * 64 + ln];
+    uint32_t out[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      float f = 0.0f;
+      uint64_t x = mq.lift;
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const uint32_t sc = (sw[c] >> (8 * e)) & 0xFFu;
+        f += (float)sc * K.invm[c];
+        x += (uint64_t)sc * K.w[li][c];
+      }
+      const uint32_t kappa = (uint32_t)floorf(f + 0.5f);
+      x -= (uint64_t)kappa * K.Mq[li];
+      out[e] = mq.q < 0x80000000u ? reduce_u64_q31(x, mq.mu, mq.q) : reduce_u64(x, mq);
+    }
+    uint32_t* Cout = P.c + gprod * P.n + (size_t)u * P.t;
+    if (zb + 3 < (int)P.t) {
+      *(uint4*)(Cout + zb) = make_uint4(out[0], out[1], out[2], out[3]);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (zb + e < (int)P.t) Cout[zb + e] = out[e];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Two-phase form for one product in 2 x 2 tiles with C = 8 or 9 channels, whose
+// C residue planes would hold a workgroup of their own per CU (9 x 14 KiB at
+// n = 4096).  A workgroup of eight waves stages and multiplies channels
+// [0, CA) (CA = ceil(C / 2)), then [CA, C), each phase in planes 0.. of the
+// same LDS; its largest LDS use is 76 KiB, so two workgroups share a CU and one
+// stages or reconstructs while the other multiplies.  Within a phase of CP
+// channels: CP = 5 puts channels 0-3 on waves 0-3 and channel 4 on waves 4-7
+// in K quarters; CP = 4 puts channel k on waves k and k + 4 in K halves (every
+// SIMD gets the same matrix work).  A K part other than a channel's first hands
+// over its partial sums as residues mod m (one byte per output: T mod m is all
+// the reconstruction needs, and it is additive), which the first part adds in
+// before forming s = (T mod m) (M/m)^-1 mod m.  The s bytes of phase 0 go just
+// past phase 1's planes, those of phase 1 just below, so the reconstruction finds
+// all C channels in one run of LDS.
+// ---------------------------------------------------------------------------
+template <int CP>
+struct CrtPhaseWaves {
+  static_assert(CP == 4 || CP == 5, "phases of four or five channels");
+  static constexpr int kOtherParts = CP == 4 ? 4 : 3;  // parts that hand over residues
+  __device__ static void role(int w, int& ch, int& part, int& parts) {
+    if (CP == 4) { ch = w & 3; part = w >> 2; parts = 2; return; }
+    if (w < 4) { ch = w; part = 0; parts = 1; return; }
+    ch = 4; part = w - 4; parts = 4;
+  }
+  __device__ static int other_slot(int ch, int part) { return CP == 4 ? ch : part - 1; }
+};
+
+template <int C>
+__host__ __device__ constexpr uint32_t crt_phase_lds(uint32_t plane_bytes) {
+  constexpr uint32_t CA = (C + 1) / 2, CB = C - CA;
+  const uint32_t p0 = CA * plane_bytes, p1 = CB * plane_bytes + CA * kCrtSBytes;
+  return p0 > p1 ? p0 : p1;
+}
+
+// One phase: channels [c0, c0 + CP) staged, multiplied and turned into s bytes at sbase.
+template <int CP>
+__device__ __forceinline__ void crt_phase(const Mfma32Params& P, const CrtConsts& K, const GroupInfo& gi,
+                                          const CrtUnit (&un)[4], uint8_t* smem, int c0, uint32_t sbase) {
+  constexpr int NT = 8 * 64;
+  const uint32_t nitems = gi.nslots * (P.n >> 1);
+  for (uint32_t base = 0; base < nitems; base += kStageItems * NT)
+    crt_stage_pass<CP, NT>(P, K, gi, smem, base, nitems, c0);
+  stage_zero_fill<CP, NT>(P, gi, smem);
+  __syncthreads();
+  const int wave = (int)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  int ch, part, parts;
+  CrtPhaseWaves<CP>::role(wave, ch, part, parts);
+  v16i acc[4];
+  const int steps = (int)(P.r << P.log2spd);
+  crt_channel_loop<true>(P, smem, ch, CP, un, gi.v_lo, part * steps / parts, (part + 1) * steps / parts, acc);
+  __syncthreads();  // the planes are read for the last time
+  const int gc = c0 + ch;
+  const uint32_t m = K.m[gc];
+  uint32_t* other = (uint32_t*)smem;  // [slot][4 units][4 blk][64 lanes], four residue bytes a dword
+  if (part > 0) {
+    const int sl = CrtPhaseWaves<CP>::other_slot(ch, part);
+    const uint32_t magic = K.magic[gc], off = K.off[gc];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int blk = 0; blk < 4; ++blk) {
+        uint32_t w = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) w |= signed_mod(acc[i][4 * blk + e], m, magic, off) << (8 * e);
+        other[((sl * 4 + i) * 4 + blk) * 64 + lane] = w;
+      }
+  }
+  __syncthreads();
+  if (part == 0) {
+    uint32_t* sb = (uint32_t*)(smem + sbase);
+    const uint32_t y = K.y[gc], yp = K.yp[gc], oy = K.oy[gc];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int blk = 0; blk < 4; ++blk) {
+        int32_t T[4] = {acc[i][4 * blk], acc[i][4 * blk + 1], acc[i][4 * blk + 2], acc[i][4 * blk + 3]};
+        for (int pp = 1; pp < parts; ++pp) {
+          const uint32_t w = other[((CrtPhaseWaves<CP>::other_slot(ch, pp) * 4 + i) * 4 + blk) * 64 + lane];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) T[e] += (int32_t)((w >> (8 * e)) & 0xFFu);
+        }
+        uint32_t sw = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) sw |= crt_s(T[e], m, y, yp, oy) << (8 * e);
+        sb[((ch * 4 + i) * 4 + blk) * 64 + lane] = sw;
+      }
+  }
+  __syncthreads();  // the residue bytes are read before the next phase stages over them
+}
+
+template <int C>
+__global__ __launch_bounds__(8 * 64) __attribute__((amdgpu_waves_per_eu(4, 4)))
+void crt_phase_kernel(const Mfma32Params P, const CrtConsts K) {
+  static_assert(C == 8 || C == 9, "two phases of four or five channels");
+  constexpr int CA = (C + 1) / 2, CB = C - CA;
+  constexpr int NT = 8 * 64;
+  extern __shared__ __align__(16) uint8_t smem[];
+  const uint64_t grp = blockIdx.x;
+  const GroupInfo gi = group_info(P, grp);
+  CrtUnit un[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) un[i] = crt_unit(P, gi, grp, i);
+  const uint32_t plane_bytes = P.a_plane + P.b_plane;
+  const uint32_t sb0 = CB * plane_bytes;                // s bytes of channels [0, CA)
+  const uint32_t sb1 = sb0 - CB * kCrtSBytes;           // s bytes of channels [CA, C)
+  crt_phase<CA>(P, K, gi, un, smem, 0, sb0);
+  crt_phase<CB>(P, K, gi, un, smem, CA, sb1);
+
+  // ---- reconstruction (as in crt_wave_kernel), channel c's s bytes at
+  // sb0 + c * kCrtSBytes for c < CA, sb1 + (c - CA) * kCrtSBytes after
+  for (int idx = threadIdx.x; idx < 4 * 4 * 64; idx += NT) {
+    const int i = idx >> 8, blk = (idx >> 6) & 3, ln = idx & 63;
+    const CrtUnit ui = crt_unit(P, gi, grp, i);
+    if (!ui.valid) continue;
+    const int u = ui.u0 + (ln & 31);
+    const int zb = ui.z0 + 8 * blk + 4 * (ln >> 5);
+    if (u >= (int)P.r || zb >= (int)P.t) continue;
+    uint32_t li;
+    const uint64_t gprod = global_product(P, gi.first + (uint64_t)ui.slot, &li);
+    const ModQ32 mq = P.mods[li];
+    uint32_t sw[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const uint32_t* sb = (const uint32_t*)(smem + (c < CA ? sb0 + c * kCrtSBytes : sb1 + (c - CA) * kCrtSBytes));
+      sw[c] = sb[(i * 4 + blk) * 64 + ln];
+    }
     uint32_t out[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {

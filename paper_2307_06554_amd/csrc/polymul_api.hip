@@ -417,6 +417,18 @@ polymul_status launch_crt_CS(const Mfma32Params& P, const CrtConsts& K, uint32_t
   return launch_status();
 }
 
+template <int C> const void* k_crt_phase() { return (const void*)crt_phase_kernel<C>; }
+
+template <int C>
+polymul_status launch_crt_phase(const Mfma32Params& P, const CrtConsts& K, hipStream_t s) {
+  if (allow_lds<k_crt_phase<C>>() != POLYMUL_OK) return POLYMUL_EDEVICE;
+  const uint64_t groups = ((P.nprod << P.log2U) + 3) / 4;
+  if (groups > 0x7FFFFFFFull) return POLYMUL_EUNSUPPORTED;
+  const uint32_t lds = crt_phase_lds<C>(P.a_plane + P.b_plane);
+  hipLaunchKernelGGL((crt_phase_kernel<C>), dim3((uint32_t)groups), dim3(8 * 64), lds, s, P, K);
+  return launch_status();
+}
+
 // Dynamic LDS: the residue planes, or the combine step's bytes laid over them if larger.
 template <int C, bool SMALL>
 polymul_status launch_crt_C(const Mfma32Params& P, const CrtConsts& K, uint32_t lds, hipStream_t s) {
@@ -424,6 +436,12 @@ polymul_status launch_crt_C(const Mfma32Params& P, const CrtConsts& K, uint32_t 
   if (lds > kMaxLds) return POLYMUL_EUNSUPPORTED;
   // one product in 2 x 2 tiles per group: the four tiles share A by row and B by column
   const bool share22 = !SMALL && P.log2U == 2 && P.tz == 2 && P.slots == 1;
+  if constexpr (!SMALL && (C == 8 || C == 9)) {
+    // all C planes hold a CU alone: stage and multiply the channels in two phases
+    // so that two workgroups share a CU
+    if (share22 && 2 * lds > kMaxLds && 2 * crt_phase_lds<C>(P.a_plane + P.b_plane) <= kMaxLds)
+      return launch_crt_phase<C>(P, K, s);
+  }
   return share22 ? launch_crt_CS<C, SMALL, true>(P, K, lds, s) : launch_crt_CS<C, SMALL, false>(P, K, lds, s);
 }
 
