@@ -292,7 +292,9 @@ def main():
            "vs_limbs": ms / ms_c, "moduli": pm.polymul_crt_moduli(n, max(w.qs)),
            "mfma_ops_per_step": 2 * chans * n * n * products,
            "lds_read_tb_per_s": lds_bytes / (ms_c / 1e3) / 1e12, "bound": "lds",
-           "bit_identical_to_limbs": None, "kernel": f"crt_group_kernel<{chans},false>"}
+           "bit_identical_to_limbs": None,
+           # at n = 4096 eight or nine channels run in two phases, two workgroups per CU
+           "kernel": f"crt_phase_kernel<{chans}>" if chans in (8, 9) else f"crt_wave_kernel<{chans}>"}
     pm.polymul_negacyclic_rns(a, b, w.qs, out=c)
     torch.cuda.synchronize()
     crt["bit_identical_to_limbs"] = bool(torch.equal(cc, c))
