@@ -291,7 +291,8 @@ def main():
     crt = {"value": products / (ms_c / 1e3), "unit": "polymuls/s", "ms_per_step": ms_c,
            "vs_limbs": ms / ms_c, "moduli": pm.polymul_crt_moduli(n, max(w.qs)),
            "mfma_ops_per_step": 2 * chans * n * n * products,
-           "lds_read_tb_per_s": lds_bytes / (ms_c / 1e3) / 1e12, "bound": "lds",
+           "lds_read_tb_per_s": lds_bytes / (ms_c / 1e3) / 1e12,
+           "bound": "issue: per MFMA, half an A run to read and align and half a B run",
            "bit_identical_to_limbs": None,
            # at n = 4096 eight or nine channels run in two phases, two workgroups per CU
            "kernel": f"crt_phase_kernel<{chans}>" if chans in (8, 9) else f"crt_wave_kernel<{chans}>"}
