@@ -285,9 +285,9 @@ def main():
     cc = torch.empty_like(a)
     ms_c = time_steps(lambda: pm.polymul_negacyclic_rns_crt(a, b, w.qs, out=cc), args.steps, args.warmup)
     chans = len(pm.polymul_crt_moduli(n, max(w.qs)))
-    # LDS read instructions per MFMA: five dwords of A (two ds_read2_b32, one ds_read_b32) and a
-    # ds_read_b128 of B, one fragment each per residue channel; bytes per wave64 MFMA:
-    lds_bytes = products * 4 * chans * (n // 32) * 64 * (20 + 16)  # 4 tiles, n/32 K-steps
+    # LDS bytes read per lane and K-step of one channel: two A runs (five dwords each) and two
+    # B runs (16 bytes each) feed the four MFMAs of a product's 2 x 2 tiles
+    lds_bytes = products * chans * (n // 32) * 64 * (2 * 20 + 2 * 16)  # n/32 K-steps, 64 lanes
     crt = {"value": products / (ms_c / 1e3), "unit": "polymuls/s", "ms_per_step": ms_c,
            "vs_limbs": ms / ms_c, "moduli": pm.polymul_crt_moduli(n, max(w.qs)),
            "mfma_ops_per_step": 2 * chans * n * n * products,
