@@ -94,6 +94,28 @@ def time_steps(fn, steps, warmup):
     return e0.elapsed_time(e1) / steps
 
 
+def int8_gemm_reference(achieved_tops, seconds=0.5, reps=10):
+    """The vendor library's int8 GEMM (hipBLASLt through torch._int_mm) on random
+    int8 operands of 8192 x 8192 x 8192, timed like the headline: what the chip
+    sustains on a plain dense int8 contraction, beside the published peak.  A
+    reference measurement only; nothing of the polynomial path runs through it."""
+    import torch
+    M = K = N = 8192
+    try:
+        g = torch.Generator(device="cuda")
+        g.manual_seed(1)
+        x = torch.randint(-128, 128, (M, K), dtype=torch.int8, device="cuda", generator=g)
+        y = torch.randint(-128, 128, (K, N), dtype=torch.int8, device="cuda", generator=g)
+        run = lambda: torch._int_mm(x, y)
+        preheat(run, seconds)
+        ms = time_steps(run, reps, 2)
+    except (RuntimeError, AttributeError) as exc:  # int8 GEMM not provided by this torch build
+        return {"library": "torch._int_mm", "error": str(exc)[:200]}
+    tops = 2 * M * K * N / (ms / 1e3) / 1e12
+    return {"library": "hipBLASLt (torch._int_mm)", "shape": [M, K, N], "ms": ms, "tops": tops,
+            "headline_vs_library": achieved_tops / tops}
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -329,6 +351,7 @@ def main():
                       "mfma_speedup": value / plain_value,
                       "tmac_per_s": products * n * n / (ms_plain / 1e3) / 1e12,
                       "kernel": "plain_kernel (v_mad_u64_u32 per 32x32-bit term, lazy folds)"},
+        "int8_gemm_reference": int8_gemm_reference(achieved_tops),
     }
     out["parity"] = None
     if not args.no_cpu_baseline:
