@@ -14,7 +14,9 @@
 //
 // A workgroup stages `slots` consecutive products (up to 16) and its four waves
 // take the (product, tile) units in turn; the digit planes, the limb split, the
-// shift classes and the epilogue are those of the resident kernel.
+// shift classes and the epilogue are those of the resident kernel.  SHB (one b
+// for every product of the launch, Sec. 4 fine-tuning (i)): b's digit rows are
+// staged once per workgroup, ahead of the slots' A planes.
 #pragma once
 #include "pm_mfma32.h"
 
@@ -99,11 +101,14 @@ __device__ __forceinline__ void mfma16_reduce(const Mfma32Params& P, const ModQ3
 
 // Stage the group's slots: word group j of a (j < n/4) and of b (n/4 <= j < n/2)
 // of every slot, kPrefetch loads per thread in flight before any is converted.
-template <int L>
+// SHB: items [0, nslots n/4) are the slots' a word groups, the last n/4 b's
+// (from slot 0's product), written once to the B planes at bshared; slot s's A
+// planes at smem + s * L * a_plane.
+template <int L, bool SHB = false>
 __device__ __forceinline__ void stage16(const Mfma32Params& P, const Slot16* tab, uint32_t nslots, uint8_t* smem,
-                                        int v_lo) {
-  const uint32_t half = P.n >> 1, quarter = P.n >> 2, log2half = P.log2n - 1;
-  const uint32_t nitems = nslots << log2half;
+                                        int v_lo, uint8_t* bshared = nullptr) {
+  const uint32_t half = P.n >> 1, quarter = P.n >> 2, log2half = P.log2n - 1, log2q = P.log2n - 2;
+  const uint32_t nitems = SHB ? (nslots + 1) << log2q : nslots << log2half;
   for (uint32_t base = 0; base < nitems; base += kPrefetch * kThreads) {
     uint4 pf[kPrefetch];
 #pragma unroll
@@ -111,21 +116,35 @@ __device__ __forceinline__ void stage16(const Mfma32Params& P, const Slot16* tab
       const uint32_t i = base + threadIdx.x + k * kThreads;
       pf[k] = make_uint4(0, 0, 0, 0);
       if (i < nitems) {
-        const Slot16& sl = tab[i >> log2half];
-        const uint32_t j = i & (half - 1);
-        pf[k] = j < quarter ? ((const uint4*)(P.a + (((uint64_t)sl.a_hi << 32) | sl.a_lo)))[j]
-                            : ((const uint4*)(P.b + (((uint64_t)sl.b_hi << 32) | sl.b_lo)))[j - quarter];
+        if (SHB) {
+          const uint32_t s = i >> log2q, j = i & (quarter - 1);
+          const Slot16& sl = tab[s < nslots ? s : 0];
+          pf[k] = s < nslots ? ((const uint4*)(P.a + (((uint64_t)sl.a_hi << 32) | sl.a_lo)))[j]
+                             : ((const uint4*)(P.b + (((uint64_t)sl.b_hi << 32) | sl.b_lo)))[j];
+        } else {
+          const Slot16& sl = tab[i >> log2half];
+          const uint32_t j = i & (half - 1);
+          pf[k] = j < quarter ? ((const uint4*)(P.a + (((uint64_t)sl.a_hi << 32) | sl.a_lo)))[j]
+                              : ((const uint4*)(P.b + (((uint64_t)sl.b_hi << 32) | sl.b_lo)))[j - quarter];
+        }
       }
     }
 #pragma unroll
     for (int k = 0; k < kPrefetch; ++k) {
       const uint32_t i = base + threadIdx.x + k * kThreads;
       if (i < nitems) {
-        const uint32_t s = i >> log2half, j = i & (half - 1);
-        const ModQ32& m = P.mods[tab[s].li];
-        uint8_t* slot = smem + s * P.slot_bytes;
-        if (j < quarter) stage_a_item<L>(P, slot, j, pf[k], m);
-        else stage_b_item<L>(P, slot + L * P.a_plane, v_lo, j - quarter, pf[k], m);
+        if (SHB) {
+          const uint32_t s = i >> log2q, j = i & (quarter - 1);
+          const ModQ32& m = P.mods[tab[s < nslots ? s : 0].li];
+          if (s < nslots) stage_a_item<L>(P, smem + s * L * P.a_plane, j, pf[k], m);
+          else stage_b_item<L>(P, bshared, v_lo, j, pf[k], m);
+        } else {
+          const uint32_t s = i >> log2half, j = i & (half - 1);
+          const ModQ32& m = P.mods[tab[s].li];
+          uint8_t* slot = smem + s * P.slot_bytes;
+          if (j < quarter) stage_a_item<L>(P, slot, j, pf[k], m);
+          else stage_b_item<L>(P, slot + L * P.a_plane, v_lo, j - quarter, pf[k], m);
+        }
       }
     }
   }
@@ -134,8 +153,8 @@ __device__ __forceinline__ void stage16(const Mfma32Params& P, const Slot16* tab
   const int row_dw = (int)(P.rowlen >> 2);
   const int zr0 = (int)P.r - v_lo;
   const int nz = ((int)P.b_rows - zr0) * row_dw;
-  for (uint32_t s = 0; s < nslots; ++s) {
-    uint8_t* bbase = smem + s * P.slot_bytes + L * P.a_plane;
+  for (uint32_t s = 0; s < (SHB ? 1u : nslots); ++s) {
+    uint8_t* bbase = SHB ? bshared : smem + s * P.slot_bytes + L * P.a_plane;
     for (int e = threadIdx.x; e < nz; e += kThreads) {
       const int row = zr0 + e / row_dw, wd = e % row_dw;
 #pragma unroll
@@ -145,8 +164,9 @@ __device__ __forceinline__ void stage16(const Mfma32Params& P, const Slot16* tab
 }
 
 // One group of P.slots consecutive products (the last group may hold fewer).
-template <int L>
-__device__ __forceinline__ void small_group(const Mfma32Params& P, uint64_t grp, uint8_t* smem, Slot16* tab) {
+template <int L, bool SHB = false>
+__device__ __forceinline__ void small_group(const Mfma32Params& P, uint64_t grp, uint8_t* smem, Slot16* tab,
+                                            uint8_t* bshared = nullptr) {
   const uint64_t first = grp * P.slots;
   const uint64_t left = P.nprod - first;
   const uint32_t nslots = left < P.slots ? (uint32_t)left : P.slots;
@@ -158,7 +178,7 @@ __device__ __forceinline__ void small_group(const Mfma32Params& P, uint64_t grp,
   }
   __syncthreads();
   const int v_lo = -((int)P.r - 1);
-  stage16<L>(P, tab, nslots, smem, v_lo);
+  stage16<L, SHB>(P, tab, nslots, smem, v_lo, bshared);
   __syncthreads();
 
   const uint32_t lane = threadIdx.x & 63, wave = wave_uniform(threadIdx.x >> 6);
@@ -169,8 +189,8 @@ __device__ __forceinline__ void small_group(const Mfma32Params& P, uint64_t grp,
   for (uint32_t unit = wave; unit < units; unit += 4) {
     const uint32_t s = unit >> P.log2U, tile = unit & (U - 1);
     const int u0 = 16 * (int)tile;
-    const uint8_t* slot = smem + s * P.slot_bytes;
-    const uint8_t* bplane = slot + L * P.a_plane;
+    const uint8_t* slot = smem + s * (SHB ? L * P.a_plane : P.slot_bytes);
+    const uint8_t* bplane = SHB ? bshared : slot + L * P.a_plane;
     // lane (zl, g), K-step st: d = 4 st + g; A run at S = E - (16 d + zl), B row u0 + zl - d
     const int S0 = (int)P.E - 16 * g - zl;
     const int B0 = (u0 + zl - g - v_lo) * (int)P.b_rowstride;
@@ -191,12 +211,18 @@ __device__ __forceinline__ void small_group(const Mfma32Params& P, uint64_t grp,
   }
 }
 
-// Dynamic LDS: the slots' digit planes, then the slot table.
-template <int L>
+// Dynamic LDS: the slots' digit planes, then the slot table.  SHB: the slots'
+// A planes, the B planes of the shared b, then the slot table.
+template <int L, bool SHB>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void mfma16_group_kernel(const Mfma32Params P) {
   extern __shared__ __align__(16) uint8_t smem[];
-  small_group<L>(P, blockIdx.x, smem, (Slot16*)(smem + P.slots * P.slot_bytes));
+  if constexpr (SHB) {
+    uint8_t* bshared = smem + P.slots * L * P.a_plane;
+    small_group<L, true>(P, blockIdx.x, smem, (Slot16*)(bshared + L * P.b_plane), bshared);
+  } else {
+    small_group<L>(P, blockIdx.x, smem, (Slot16*)(smem + P.slots * P.slot_bytes));
+  }
 }
 
 }  // namespace pm

@@ -281,7 +281,7 @@ template <int L, typename W, int WPE> const void* k_stream() { return (const voi
 template <typename W> const void* k_stream8() { return (const void*)stream8_kernel<W>; }
 const void* k_grouped() { return (const void*)grouped_kernel; }
 template <int L> const void* k_shared() { return (const void*)mfma32_shared_kernel<L>; }
-template <int L> const void* k_small() { return (const void*)mfma16_group_kernel<L>; }
+template <int L, bool SHB> const void* k_small() { return (const void*)mfma16_group_kernel<L, SHB>; }
 
 template <int L, bool SMALL>
 polymul_status launch_mfma32_L(const Mfma32Params& P, uint32_t lds, hipStream_t s) {
@@ -296,15 +296,21 @@ polymul_status launch_mfma32_L(const Mfma32Params& P, uint32_t lds, hipStream_t 
 // two rounds of workgroups per CU (at least four, so that every wave has a tile).
 template <int L>
 polymul_status launch_small_L(Mfma32Params P, hipStream_t s) {
-  if (allow_lds<k_small<L>>() != POLYMUL_OK) return POLYMUL_EDEVICE;
+  // one b for every product (one channel): its rows are staged once per workgroup
+  const bool shb = P.b_shared && P.lc == 1 && P.lrep == 1;
+  if (shb ? allow_lds<k_small<L, true>>() != POLYMUL_OK : allow_lds<k_small<L, false>>() != POLYMUL_OK)
+    return POLYMUL_EDEVICE;
+  const uint64_t per_slot = shb ? (uint64_t)L * P.a_plane : P.slot_bytes;
+  const uint64_t fixed = (shb ? (uint64_t)L * P.b_plane : 0) + kSlots16 * sizeof(Slot16);
   uint32_t slots = kSlots16;
   while (slots > 4 && (P.nprod + slots - 1) / slots < 2ull * device_cus()) slots /= 2;
-  while (slots > 1 && (uint64_t)slots * P.slot_bytes + kSlots16 * sizeof(Slot16) > kMaxLds / 2) slots /= 2;
+  while (slots > 1 && slots * per_slot + fixed > kMaxLds / 2) slots /= 2;
   P.slots = slots;
   const uint64_t groups = (P.nprod + slots - 1) / slots;
   if (groups > 0x7FFFFFFFull) return POLYMUL_EUNSUPPORTED;
-  const uint32_t lds = slots * P.slot_bytes + kSlots16 * (uint32_t)sizeof(Slot16);  // planes, then the slot table
-  hipLaunchKernelGGL((mfma16_group_kernel<L>), dim3((uint32_t)groups), dim3(kThreads), lds, s, P);
+  const uint32_t lds = (uint32_t)(slots * per_slot + fixed);  // planes, then the slot table
+  if (shb) hipLaunchKernelGGL((mfma16_group_kernel<L, true>), dim3((uint32_t)groups), dim3(kThreads), lds, s, P);
+  else hipLaunchKernelGGL((mfma16_group_kernel<L, false>), dim3((uint32_t)groups), dim3(kThreads), lds, s, P);
   return launch_status();
 }
 
