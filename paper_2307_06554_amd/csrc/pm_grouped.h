@@ -42,8 +42,11 @@ __device__ __forceinline__ void small_item(const Mfma32Params& P, uint32_t index
   small_group<L>(P, index, smem, (Slot16*)(smem + P.slots * P.slot_bytes));
 }
 
-// Workgroup b starts with item b (the grid is no larger than the list), and every
-// later item comes from the queue, whose k-th claim is item grid + k.  The claim of
+// The first grid items (largest first) are dealt out statically: workgroup b < G/2
+// takes item b and workgroup G/2 + k item G - 1 - k (G = grid, no larger than the
+// list), so that the workgroups the dispatcher places on one CU first, b and b + G/2,
+// pair a larger item with a smaller one; every later item comes from the queue,
+// whose k-th claim is item G + k.  The claim of
 // a workgroup's next item is issued when its current item starts and read when it
 // ends, so that the atomic's round trip overlaps the current item's work.
 // counter[0] is the queue, counter[1] counts the workgroups that have left; the last
@@ -55,7 +58,8 @@ void grouped_kernel(const GroupJob* __restrict__ jobs, const WorkItem* __restric
                     uint32_t* counter) {
   extern __shared__ __align__(16) uint8_t smem[];
   __shared__ uint32_t next_item;
-  uint32_t it = blockIdx.x;
+  const uint32_t half = gridDim.x >> 1;
+  uint32_t it = blockIdx.x < half ? blockIdx.x : gridDim.x - 1 - (blockIdx.x - half);
   for (;;) {
     uint32_t claim = 0;
     if (threadIdx.x == 0) claim = atomicAdd(counter, 1u) + gridDim.x;  // waited for at the end of the item
