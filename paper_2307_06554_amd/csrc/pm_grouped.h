@@ -46,9 +46,9 @@ __device__ __forceinline__ void small_item(const Mfma32Params& P, uint32_t index
 // takes item b and workgroup G/2 + k item G - 1 - k (G = grid, no larger than the
 // list), so that the workgroups the dispatcher places on one CU first, b and b + G/2,
 // pair a larger item with a smaller one; every later item comes from the queue,
-// whose k-th claim is item G + k.  The claim of
-// a workgroup's next item is issued when its current item starts and read when it
-// ends, so that the atomic's round trip overlaps the current item's work.
+// whose k-th claim is item G + k.  A workgroup claims its next item when its current
+// one is done, so that the queue hands the remaining items (the smallest) to the
+// workgroups that come free first; a list no longer than the grid needs no queue.
 // counter[0] is the queue, counter[1] counts the workgroups that have left; the last
 // to leave sets both back to zero, so that the next launch (a graph replay) starts
 // from an empty queue without a reset node.  Every workgroup's final claim has
@@ -60,9 +60,8 @@ void grouped_kernel(const GroupJob* __restrict__ jobs, const WorkItem* __restric
   __shared__ uint32_t next_item;
   const uint32_t half = gridDim.x >> 1;
   uint32_t it = blockIdx.x < half ? blockIdx.x : gridDim.x - 1 - (blockIdx.x - half);
+  const bool queue = nitems > gridDim.x;
   for (;;) {
-    uint32_t claim = 0;
-    if (threadIdx.x == 0) claim = atomicAdd(counter, 1u) + gridDim.x;  // waited for at the end of the item
     const WorkItem w = items[it];
     const GroupJob& job = jobs[w.group];
     if (job.kind == kJobResident) {
@@ -80,7 +79,8 @@ void grouped_kernel(const GroupJob* __restrict__ jobs, const WorkItem* __restric
     } else {
       stream_block<4, uint32_t>(job.sp, w.index, smem);
     }
-    if (threadIdx.x == 0) next_item = claim;
+    if (!queue) break;  // every item was dealt out: no claims, nothing to reset
+    if (threadIdx.x == 0) next_item = atomicAdd(counter, 1u) + gridDim.x;
     __syncthreads();  // LDS is reused by the next item; next_item is visible
     it = next_item;
     if (it >= nitems) {  // uniform: every wave leaves together

@@ -236,11 +236,12 @@ __device__ __forceinline__ void mfma_step_pp(v16i (&acc)[2 * L - 1], const v4i (
 template <int L>
 __device__ __forceinline__ void mfma32_tile(const Mfma32Params& P, const uint8_t* aplane, const uint8_t* bplane,
                                             int z0, int u0, int v_lo, v16i (&acc)[2 * L - 1], int st_lo = 0,
-                                            int st_hi = -1) {
+                                            int st_hi = -1, int E = -1) {
   const int lane = threadIdx.x & 63;
   const int zl = lane & 31, g = lane >> 5;
-  // A: lane reads reversed positions S .. S+15 with S = E - (d t + z - w0 - 16 g).
-  const int S0 = (int)P.E - (z0 + zl) + 16 * g;
+  // A: lane reads reversed positions S .. S+15 with S = E - (d t + z - w0 - 16 g)
+  // (E: the ext index at reversed position 0, P.E unless a K window says otherwise).
+  const int S0 = (E < 0 ? (int)P.E : E) - (z0 + zl) + 16 * g;
   // B: lane reads row (u - d) - v_lo, bytes w0 + 16 g .. + 15.
   const int B0 = (u0 + zl - v_lo) * (int)P.b_rowstride + 16 * g;
   const int steps = st_hi < 0 ? (int)(P.r << P.log2spd) : st_hi;  // one past the last K-step
@@ -437,9 +438,11 @@ __device__ __forceinline__ const uint4* item_src(const Mfma32Params& P, const Gr
 // Word group a[4j .. 4j+3] into the reversed ext planes at abase: dword
 // (E+1)/4 - 1 - j, byte k holding ext[4j + 3 - k], and its negated copy n/4
 // dwords further when that lands inside the window.
-template <int L>
+// kWin: the plane holds a K window (E below n - 1), so the positive copy may fall
+// outside it too (dw "below zero" wraps to a large unsigned value and is skipped).
+template <int L, bool kWin = false>
 __device__ __forceinline__ void stage_a_item(const Mfma32Params& P, uint8_t* abase, uint32_t j, uint4 x,
-                                             const ModQ32& m) {
+                                             const ModQ32& m, uint32_t E) {
   const uint32_t q = m.q, thr = m.thr, quarter = P.n >> 2;
   const uint32_t xr[4] = {reduce_u32(x.w, m), reduce_u32(x.z, m), reduce_u32(x.y, m), reduce_u32(x.x, m)};
   uint32_t w[4], nw[4];
@@ -447,10 +450,15 @@ __device__ __forceinline__ void stage_a_item(const Mfma32Params& P, uint8_t* aba
 #pragma unroll
   for (int k = 0; k < 4; ++k)
     if (P.cyclic) nw[k] = w[k];
-  const uint32_t dw = ((P.E + 1) >> 2) - 1 - j;
-  transpose_store<L>(abase, P.a_plane, dw * 4, w);
+  const uint32_t dw = ((E + 1) >> 2) - 1 - j;
+  if (!kWin || dw < (P.a_plane >> 2)) transpose_store<L>(abase, P.a_plane, dw * 4, w);
   const uint32_t dwn = dw + quarter;
   if (dwn < (P.a_plane >> 2)) transpose_store<L>(abase, P.a_plane, dwn * 4, nw);
+}
+template <int L>
+__device__ __forceinline__ void stage_a_item(const Mfma32Params& P, uint8_t* abase, uint32_t j, uint4 x,
+                                             const ModQ32& m) {
+  stage_a_item<L, false>(P, abase, j, x, m, P.E);
 }
 
 // Word group e of b (row vs = e / (t/4), words 4wd..) into the staged B rows at
@@ -663,26 +671,112 @@ __device__ __forceinline__ void resident_group(const Mfma32Params& P, uint64_t g
   resident_compute<L>(P, grp, gi, smem);
 }
 
-// One run of a K-split group (one product, U >= 4: every wave has a tile):
-// K-steps [part, part + 1) * steps / kparts of all four tiles, residues stored
-// in the run's copy of c.
+// The K window of one run of a K-split group (one product, t >= 32, so the group's
+// tiles cover every z): K-steps [st_lo, st_hi) touch d in [d_lo, d_hi), hence
+// ext[d_lo t - t + 1 .. d_hi t - 1], held with E = d_hi t - 1 at reversed position 0,
+// and B rows v = u - d for the group's u, from v_lo = u_lo - d_hi + 1 on (the host
+// sizes a_plane and b_rows for the widest run).  The staged items are the runs of 64
+// word groups (a's, then b's; n >= 256) that hold a byte of the window: up to two
+// ranges of a (positive and negated copies) and two of b (rows v and v - r).
+struct KWindow {
+  uint32_t E;
+  int v_lo;
+  uint32_t lo[4], cnt[4];  // item-run ranges within the product, in order, disjoint
+};
+
+// Range i (a constant after unrolling: no dynamic index, nothing in scratch) of the
+// runs holding items [lo, hi) (+ base runs); the ranges come in order of lo, and each
+// starts where the previous ones end, so that no run is staged twice.
+__device__ __forceinline__ void kwin_range(KWindow& w, int i, int& end, int lo, int hi, int base) {
+  int rlo = base + (lo >> 6), rhi = base + ((hi + 63) >> 6);
+  if (lo >= hi) rlo = rhi = end;
+  rlo = max(rlo, end);
+  rhi = max(rhi, rlo);
+  w.lo[i] = (uint32_t)rlo;
+  w.cnt[i] = (uint32_t)(rhi - rlo);
+  end = rhi;
+}
+
+__device__ __forceinline__ KWindow k_window(const Mfma32Params& P, const GroupInfo& gi, int st_lo, int st_hi) {
+  const int t = (int)P.t, r = (int)P.r, q4 = (int)(P.n >> 2);
+  const int d_lo = st_lo >> P.log2spd, d_hi = ((st_hi - 1) >> P.log2spd) + 1;
+  KWindow w;
+  w.E = (uint32_t)(d_hi * t - 1);
+  w.v_lo = gi.v_lo + r - d_hi;  // group_info's v_lo is u_lo - (r - 1)
+  int end = 0;
+  const int e4 = (int)((w.E + 1) >> 2), A4 = (int)(P.a_plane >> 2);
+  kwin_range(w, 0, end, max(0, e4 - A4), min(q4, e4), 0);            // positive copies: dword e4 - 1 - j
+  kwin_range(w, 1, end, max(0, e4 + q4 - A4), min(q4, e4 + q4), 0);  // negated copies, n/4 dwords further
+  const int rw = t >> 2, a_runs = (int)(P.n >> 8);                    // word groups per b row
+  kwin_range(w, 2, end, max(0, w.v_lo) * rw, min(r, w.v_lo + (int)P.b_rows) * rw, a_runs);
+  kwin_range(w, 3, end, max(0, w.v_lo + r) * rw, min(r, w.v_lo + r + (int)P.b_rows) * rw, a_runs);
+  return w;
+}
+
+// A window of n <= 8192 spans at most 64 runs, one pass of kWinPrefetch loads per
+// thread (a pass is a load latency exposed: 33 runs in two passes of eight took 1.5x
+// the time of 32 runs in one).
+constexpr int kWinPrefetch = 16;
+
+template <int L>
+__device__ __forceinline__ void stage_window(const Mfma32Params& P, const GroupInfo& gi, uint8_t* smem,
+                                             const KWindow& w) {
+  const uint32_t a_runs = P.n >> 8;
+  const uint32_t lane = threadIdx.x & 63, wave = wave_uniform(threadIdx.x >> 6);
+  const uint32_t total = w.cnt[0] + w.cnt[1] + w.cnt[2] + w.cnt[3];
+  if (wave >= total) return;
+  const uint32_t last = wave + 4 * ((total - 1 - wave) >> 2);  // this wave's last run
+  const ModQ32& m = P.mods[gi.li[0]];
+  const uint32_t* A = P.a + gi.gp[0] * P.n;
+  const uint32_t* B = P.b + b_product(P, gi.gp[0], gi.li[0]) * P.n;
+  auto run_of = [&](uint32_t v) {  // v-th staged run -> run within the product
+    if (v < w.cnt[0]) return w.lo[0] + v;
+    v -= w.cnt[0];
+    if (v < w.cnt[1]) return w.lo[1] + v;
+    v -= w.cnt[1];
+    if (v < w.cnt[2]) return w.lo[2] + v;
+    return w.lo[3] + (v - w.cnt[2]);
+  };
+  for (uint32_t v0 = wave; v0 < total; v0 += 4 * kWinPrefetch) {
+    uint4 pf[kWinPrefetch];
+#pragma unroll
+    for (int k = 0; k < kWinPrefetch; ++k) {  // every load issued (past the last run: the last again)
+      const uint32_t cr = run_of(min(v0 + 4 * k, last));
+      const uint32_t* src = cr < a_runs ? A + cr * 256u : B + (cr - a_runs) * 256u;
+      pf[k] = ((const uint4*)src)[lane];
+    }
+#pragma unroll
+    for (int k = 0; k < kWinPrefetch; ++k) {
+      if (v0 + 4 * k < total) {
+        const uint32_t cr = run_of(v0 + 4 * k);
+        if (cr < a_runs) stage_a_item<L, true>(P, smem, cr * 64 + lane, pf[k], m, w.E);
+        else stage_b_item<L>(P, smem + L * P.a_plane, w.v_lo, (cr - a_runs) * 64 + lane, pf[k], m);
+      }
+    }
+  }
+}
+
+// One run of a K-split group (one product, U >= 4: every wave has a tile, n >= 256):
+// K-steps [part, part + 1) * steps / kparts of all four tiles, from the run's K
+// window only; residues stored in the run's copy of c.
 template <int L>
 __device__ __forceinline__ void resident_group_split(const Mfma32Params& P, uint32_t item, uint8_t* smem) {
   const uint32_t grp = item / P.kparts, part = item - grp * P.kparts;
   const uint32_t U = 1u << P.log2U;
   const GroupInfo gi = group_info(P, grp);
-  stage_runs<L>(P, gi, smem);  // split groups have n >= 2048
-  stage_zero_fill<L>(P, gi, smem);
+  const int steps = (int)(P.r << P.log2spd);
+  const int st_lo = (int)(part * (uint32_t)steps / P.kparts), st_hi = (int)((part + 1) * (uint32_t)steps / P.kparts);
+  const KWindow win = k_window(P, gi, st_lo, st_hi);
+  stage_window<L>(P, gi, smem, win);
+  zero_fill_b<L>(P, smem + L * P.a_plane, win.v_lo);
   __syncthreads();
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint64_t unit = (uint64_t)grp * 4 + wave;
   const uint64_t prod = unit >> P.log2U;
   const uint32_t tile = (uint32_t)(unit & (U - 1));
   const int zt = (int)(tile % P.tz), ut = (int)(tile / P.tz);
-  const int steps = (int)(P.r << P.log2spd);
-  const int st_lo = (int)(part * (uint32_t)steps / P.kparts), st_hi = (int)((part + 1) * (uint32_t)steps / P.kparts);
   v16i acc[2 * L - 1];
-  mfma32_tile<L>(P, smem, smem + L * P.a_plane, 32 * zt, 32 * ut, gi.v_lo, acc, st_lo, st_hi);
+  mfma32_tile<L>(P, smem, smem + L * P.a_plane, 32 * zt, 32 * ut, win.v_lo, acc, st_lo, st_hi, (int)win.E);
   uint32_t li;
   const uint64_t gprod = global_product(P, prod, &li);
   uint32_t out[16];

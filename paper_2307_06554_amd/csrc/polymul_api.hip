@@ -833,14 +833,15 @@ uint64_t item_cost(const GroupJob& j) {
 }
 
 // The same for one unsplit item of a 32-bit group on its default route (resident for
-// n in [4, 4096], streamed otherwise), and the number of such items.
+// n in [4, 8192]: beyond 4096 only as K-split runs, else streamed), and the number of
+// such items.
 void default_cost(uint32_t n, uint64_t count, int L, uint64_t* items, uint64_t* cost) {
   if (n >= 64 && plan_tile(n, L) == 16) {
     const Geometry32 g = geometry32(n, 16);
     const uint32_t slots = plan_small_slots((uint32_t)L * (g.a_plane + g.b_plane));
     *items = (count + slots - 1) / slots;
     *cost = (uint64_t)slots * g.U * (n >> 6) * L * L / 2;
-  } else if (n >= 4 && n <= 4096) {
+  } else if (n >= 4 && n <= 8192) {
     const Geometry32 g = geometry32(n, plan_tile(n, L));
     *items = (count * g.U + 3) / 4;
     *cost = 4 * (uint64_t)g.r * g.spd * L * L;
@@ -849,6 +850,41 @@ void default_cost(uint32_t n, uint64_t count, int L, uint64_t* items, uint64_t* 
     *items = count * ((r + 63) / 64);
     *cost = 4 * (uint64_t)r * spd * 16 * g_plan_stream_pct.load(std::memory_order_relaxed) / 100;
   }
+}
+
+// K-split of a resident job whose item would cost `ci` > `share`: runs of K-steps
+// (a power of two of them) until a run costs at most the share.  Each run stages
+// only its K window (the K-steps' d range, D = d_hi - d_lo <= Dmax): ext positions
+// 0 .. Dmax t + t + 3 and 32 utiles + Dmax - 1 B rows, so the slot shrinks with the
+// run.  Groups of one product with a tile per wave (U >= 4, hence t >= 32) and
+// n >= 256 (the staging runs of 64 word groups) only.  Returns false (job
+// unchanged) when the job cannot or need not be split.
+bool k_window_split(GroupJob& job, uint64_t ci, uint64_t share, uint32_t* lds) {
+  Mfma32Params& P = job.rp;
+  if (P.log2U < 2 || P.n < 256 || P.t < 32) return false;
+  const uint32_t steps = P.r << P.log2spd;
+  uint32_t k = 1;
+  while (2 * k <= steps && ci / k > share) k *= 2;
+  if (k == 1) return false;
+  uint32_t dmax = 0;
+  for (uint32_t part = 0; part < k; ++part) {
+    const uint32_t st_lo = part * steps / k, st_hi = (part + 1) * steps / k;
+    dmax = std::max(dmax, ((st_hi - 1) >> P.log2spd) + 1 - (st_lo >> P.log2spd));
+  }
+  const uint32_t utiles = 4 / P.tz;  // the group's u tiles (its four tiles cover every z)
+  const uint32_t a_plane = (dmax * P.t + P.rowlen + 4 + 15) & ~15u;
+  const uint32_t b_rows = 32 * utiles + dmax - 1;
+  const uint32_t b_plane = (b_rows * P.b_rowstride + 15) & ~15u;
+  const uint32_t slot = job.L * (a_plane + b_plane);
+  if (slot > kMaxLds / 2) return false;
+  P.kparts = k;
+  P.a_plane = a_plane;
+  P.b_rows = b_rows;
+  P.b_plane = b_plane;
+  P.slot_bytes = slot;
+  P.slots = 1;
+  *lds = slot;
+  return true;
 }
 
 }  // namespace
@@ -995,17 +1031,20 @@ polymul_status polymul_plan_create(polymul_plan** plan, const polymul_group* gro
       job.kind = kJobResident;
       st = fill_mfma32(job.rp, (const uint32_t*)G.a, (const uint32_t*)G.b, (uint32_t*)G.c, n, &q32, 1, 1, 0,
                        G.count, Lg, plan_tile(n, Lg), &lds);
-      if (st == POLYMUL_OK && split && job.rp.log2U >= 2) {  // groups of one product: every wave has a tile
-        const uint32_t steps = job.rp.r << job.rp.log2spd;
-        uint32_t k = 1;
-        while (2 * k <= steps && ci / k > share) k *= 2;
-        job.rp.kparts = k;
-        if (k > 1) {
-          // an offset for now; turned into a device pointer once the buffer exists
-          job.rp.part_ws = (uint32_t*)(uintptr_t)part_words;
-          part_words += (uint64_t)k * G.count * n;
-        }
+      if (st == POLYMUL_OK && split && k_window_split(job, ci, share, &lds)) {
+        // an offset for now; turned into a device pointer once the buffer exists
+        job.rp.part_ws = (uint32_t*)(uintptr_t)part_words;
+        part_words += (uint64_t)job.rp.kparts * G.count * n;
       }
+    } else if (split && n <= 8192 &&
+               fill_mfma32(job.rp, (const uint32_t*)G.a, (const uint32_t*)G.b, (uint32_t*)G.c, n, &q32, 1, 1, 0,
+                           G.count, Lg, plan_tile(n, Lg), &lds) == POLYMUL_OK &&
+               k_window_split(job, ci, share, &lds)) {
+      // whole products too large for two workgroups per CU, K-split into windowed runs
+      job.kind = kJobResident;
+      st = POLYMUL_OK;
+      job.rp.part_ws = (uint32_t*)(uintptr_t)part_words;
+      part_words += (uint64_t)job.rp.kparts * G.count * n;
     } else {
       job.kind = kJobStream;
       const uint64_t q64 = G.q;
@@ -1065,7 +1104,7 @@ polymul_status polymul_plan_create(polymul_plan** plan, const polymul_group* gro
       }
       if (blocks > 0x7FFFFFFFull) { plan_free(p); return POLYMUL_EUNSUPPORTED; }
       p->sum_blocks = (uint32_t)blocks;
-      if (hipMalloc((void**)&p->d_segs, p->segs.size() * sizeof(SplitSeg)) != hipSuccess) {
+      if (!p->segs.empty() && hipMalloc((void**)&p->d_segs, p->segs.size() * sizeof(SplitSeg)) != hipSuccess) {
         plan_free(p);
         return POLYMUL_ENOMEM;
       }

@@ -191,3 +191,44 @@ def test_plan_small_moduli_limb_counts():
                 wv = oracle.negacyclic(a, b, q)
                 assert np.array_equal(got, wv), f"share {share}, replay {rep}, n={n}, q={q}: " + mismatch_report(got, wv)
         plan.close()
+
+
+@pytest.mark.parametrize("t", [32, 64, 128])
+def test_plan_k_window_runs(t):
+    """K-split runs stage only the window of a and the B rows their K range reads
+    (n = 8192 runs resident this way).  Every tile side, split depths from two runs
+    to one K-step per run (share 10 %), two to four limbs; n = 128 on 128-wide tiles
+    must not be split (its staging runs need n >= 256)."""
+    rng = np.random.Generator(np.random.PCG64(41 + t))
+    specs = [(8192, 1068236801, 2), (4096, 3329, 2), (2048, (1 << 24) - 3, 3), (1024, 1068236801, 3),
+             (256, 12289, 5), (128, 17, 3)]
+    groups, want = [], []
+    for n, q, count in specs:
+        a = rng.integers(0, q, size=(count, n), dtype=np.uint64).astype(np.uint32)
+        b = rng.integers(0, q, size=(count, n), dtype=np.uint64).astype(np.uint32)
+        da, db = to_dev(a), to_dev(b)
+        groups.append((da, db, torch.zeros_like(da), n, q))
+        want.append(oracle.negacyclic(a, b, q))
+    tiles = [(n, L) for n, _, _ in specs for L in (2, 3, 4) if t <= n]
+    try:
+        for n, L in tiles:
+            pm.polymul_tune_set(n, L, t)
+        for share in (10, 30, 60, 140, 1000):
+            pm.polymul_tune_param_set("plan_share_pct", share)
+            try:
+                plan = pm.Plan(groups)
+            finally:
+                pm.polymul_tune_param_set("plan_share_pct", 140)
+            for rep in range(2):
+                for g in groups:
+                    g[2].zero_()
+                plan.execute()
+                torch.cuda.synchronize()
+                for (da, db, dc, n, q), wv in zip(groups, want):
+                    got = to_host(dc, np.uint32)
+                    assert np.array_equal(got, wv), f"t={t}, share {share}, replay {rep}, n={n}, q={q}: " + \
+                        mismatch_report(got, wv)
+            plan.close()
+    finally:
+        for n, L in tiles:
+            pm.polymul_tune_set(n, L, 0)
