@@ -251,8 +251,10 @@ __device__ __forceinline__ CrtUnit crt_unit(const Mfma32Params& P, const GroupIn
 // The K loop of one channel over K-steps [st_lo, st_hi) for the group's four
 // units.  SHARE22: one product in 2 x 2 tiles (units 0..3 = (z,u) = (0,0),
 // (1,0), (0,1), (1,1)): A fragments by z, B fragments by u.  The next step's
-// fragments are read while the current step's MFMAs run.
-template <bool SHARE22>
+// fragments are read while the current step's MFMAs run.  T4: t >= 4, so every
+// K-step moves an A run by a multiple of four bytes (d t, 32-byte chunks): its
+// byte shift and dword base are then fixed for the whole loop.
+template <bool SHARE22, bool T4 = true>
 __device__ __forceinline__ void crt_channel_loop(const Mfma32Params& P, const uint8_t* smem, int ch, int C,
                                                  const CrtUnit (&un)[4], int v_lo, int st_lo, int st_hi,
                                                  v16i (&acc)[4]) {
@@ -281,13 +283,20 @@ __device__ __forceinline__ void crt_channel_loop(const Mfma32Params& P, const ui
   if (st_lo >= st_hi) return;
   auto soff = [&](int st) { return -((st >> P.log2spd) << P.log2t) + ((st & (P.spd - 1)) << 5); };
   auto boff = [&](int st) { return -(st >> P.log2spd) * rs + ((st & (P.spd - 1)) << 5); };
+  const uint32_t* apb[NA];  // T4: dword base and byte shift of each A run
+  uint32_t shb[NA];
+#pragma unroll
+  for (int i = 0; i < NA; ++i) {
+    apb[i] = ap[i] + (Sb[i] >> 2);  // Sb >= 0
+    shb[i] = (uint32_t)(Sb[i] & 3);
+  }
   uint32_t x[NA][5];
   v4i b[NB];
   auto load = [&](int st) {
     const int so = soff(st), bo = boff(st);
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
-      const uint32_t* p = ap[i] + ((Sb[i] + so) >> 2);
+      const uint32_t* p = T4 ? apb[i] + (so >> 2) : ap[i] + ((Sb[i] + so) >> 2);
 #pragma unroll
       for (int k = 0; k < 5; ++k) x[i][k] = p[k];
     }
@@ -299,7 +308,7 @@ __device__ __forceinline__ void crt_channel_loop(const Mfma32Params& P, const ui
     v4i a[NA], bc[NB];
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
-      const uint32_t sh = (uint32_t)((Sb[i] + soff(st)) & 3);
+      const uint32_t sh = T4 ? shb[i] : (uint32_t)((Sb[i] + soff(st)) & 3);
       a[i][0] = (int)__builtin_amdgcn_alignbyte(x[i][1], x[i][0], sh);
       a[i][1] = (int)__builtin_amdgcn_alignbyte(x[i][2], x[i][1], sh);
       a[i][2] = (int)__builtin_amdgcn_alignbyte(x[i][3], x[i][2], sh);
@@ -365,7 +374,7 @@ void crt_wave_kernel(const Mfma32Params P, const CrtConsts K) {
   if (ch >= 0) {
     const int steps = (int)(P.r << P.log2spd);
     const int st_lo = part * steps / parts, st_hi = (part + 1) * steps / parts;
-    crt_channel_loop<SHARE22>(P, smem, ch, C, un, gi.v_lo, st_lo, st_hi, acc);
+    crt_channel_loop<SHARE22, !SMALL>(P, smem, ch, C, un, gi.v_lo, st_lo, st_hi, acc);
   }
   __syncthreads();  // the residue planes are read for the last time
 
