@@ -232,8 +232,11 @@ __device__ __forceinline__ void mfma_step_pp(v16i (&acc)[2 * L - 1], const v4i (
 
 // One 32x32 output tile of one product: the K loop (K-steps [st_lo, st_hi), all
 // of them by default) for all L*L limb pairs, two steps per iteration so that
-// the two A fragment sets swap roles without register copies.
-template <int L>
+// the two A fragment sets swap roles without register copies.  T4: t >= 4, so a
+// K-step moves the A runs by a multiple of four bytes (d t, 32-byte chunks): the
+// byte shift and the lane's dword base are then fixed for the whole loop and each
+// step adds only a uniform offset (likewise the B rows' lane base).
+template <int L, bool T4 = true>
 __device__ __forceinline__ void mfma32_tile(const Mfma32Params& P, const uint8_t* aplane, const uint8_t* bplane,
                                             int z0, int u0, int v_lo, v16i (&acc)[2 * L - 1], int st_lo = 0,
                                             int st_hi = -1, int E = -1) {
@@ -241,7 +244,7 @@ __device__ __forceinline__ void mfma32_tile(const Mfma32Params& P, const uint8_t
   const int zl = lane & 31, g = lane >> 5;
   // A: lane reads reversed positions S .. S+15 with S = E - (d t + z - w0 - 16 g)
   // (E: the ext index at reversed position 0, P.E unless a K window says otherwise).
-  const int S0 = (E < 0 ? (int)P.E : E) - (z0 + zl) + 16 * g;
+  const int S0 = (E < 0 ? (int)P.E : E) - (z0 + zl) + 16 * g;  // >= 0
   // B: lane reads row (u - d) - v_lo, bytes w0 + 16 g .. + 15.
   const int B0 = (u0 + zl - v_lo) * (int)P.b_rowstride + 16 * g;
   const int steps = st_hi < 0 ? (int)(P.r << P.log2spd) : st_hi;  // one past the last K-step
@@ -249,29 +252,33 @@ __device__ __forceinline__ void mfma32_tile(const Mfma32Params& P, const uint8_t
   const uint32_t a_plane = P.a_plane, b_plane = P.b_plane;
 #pragma unroll
   for (int s = 0; s < 2 * L - 1; ++s) acc[s] = v16i{};
-  auto S_of = [&](int st) { return S0 - ((st >> P.log2spd) << P.log2t) + ((st & (P.spd - 1)) << 5); };
-  auto B_of = [&](int st) { return B0 - (st >> P.log2spd) * rs + ((st & (P.spd - 1)) << 5); };
+  // with T4 the lane's parts go into the plane bases and S_of / B_of are uniform
+  const uint8_t* ap = T4 ? aplane + 4 * (S0 >> 2) : aplane;
+  const uint8_t* bp = T4 ? bplane + B0 : bplane;
+  const int Sl = T4 ? 0 : S0, Bl = T4 ? 0 : B0;
+  const uint32_t sh0 = (uint32_t)(S0 & 3);
+  auto S_of = [&](int st) { return Sl - ((st >> P.log2spd) << P.log2t) + ((st & (P.spd - 1)) << 5); };
+  auto B_of = [&](int st) { return Bl - (st >> P.log2spd) * rs + ((st & (P.spd - 1)) << 5); };
+  auto sh_of = [&](int st) { return T4 ? sh0 : (uint32_t)(S_of(st) & 3); };
 
   // Steps past the end are clamped to the last one: their reads stay in bounds
   // and their results are never used.
   auto clamp = [&](int st) { return st < steps ? st : steps - 1; };
   uint32_t araw[L][5];
   v4i a0[L], a1[L], b[L];
-  const int S_first = S_of(st_lo);
-  araw_load<L>(araw, aplane, a_plane, S_first);
-  b_load<L>(b, bplane, b_plane, B_of(st_lo));
-  a_align<L>(a0, araw, (uint32_t)(S_first & 3));
-  araw_load<L>(araw, aplane, a_plane, S_of(clamp(st_lo + 1)));
+  araw_load<L>(araw, ap, a_plane, S_of(st_lo));
+  b_load<L>(b, bp, b_plane, B_of(st_lo));
+  a_align<L>(a0, araw, sh_of(st_lo));
+  araw_load<L>(araw, ap, a_plane, S_of(clamp(st_lo + 1)));
   int st = st_lo;
   for (; st + 1 < steps; st += 2) {
-    mfma_step_pp<L>(acc, a0, a1, araw, (uint32_t)(S_of(st + 1) & 3), aplane, a_plane, S_of(clamp(st + 2)), b,
-                    bplane, b_plane, B_of(st + 1));
-    mfma_step_pp<L>(acc, a1, a0, araw, (uint32_t)(S_of(clamp(st + 2)) & 3), aplane, a_plane,
-                    S_of(clamp(st + 3)), b, bplane, b_plane, B_of(clamp(st + 2)));
+    mfma_step_pp<L>(acc, a0, a1, araw, sh_of(st + 1), ap, a_plane, S_of(clamp(st + 2)), b, bp, b_plane,
+                    B_of(st + 1));
+    mfma_step_pp<L>(acc, a1, a0, araw, sh_of(clamp(st + 2)), ap, a_plane, S_of(clamp(st + 3)), b, bp, b_plane,
+                    B_of(clamp(st + 2)));
   }
   if (st < steps)
-    mfma_step_pp<L>(acc, a0, a1, araw, (uint32_t)(S_of(st) & 3), aplane, a_plane, S_of(st), b, bplane, b_plane,
-                    B_of(st));
+    mfma_step_pp<L>(acc, a0, a1, araw, sh_of(st), ap, a_plane, S_of(st), b, bp, b_plane, B_of(st));
 }
 
 // Recombination c = sum_s T_s 2^(8s) mod q of the 16 outputs a lane holds, then
@@ -616,7 +623,7 @@ __device__ __forceinline__ void stage_runs(const Mfma32Params& P, const GroupInf
 
 // The compute half of a group (after its staging barrier): each wave runs its
 // tile's K loop, then the recombination, reduction and stores.
-template <int L>
+template <int L, bool T4 = true>
 __device__ __forceinline__ void resident_compute(const Mfma32Params& P, uint64_t grp, const GroupInfo& gi,
                                                  const uint8_t* smem) {
   const uint64_t total_units = P.nprod << P.log2U;
@@ -629,7 +636,7 @@ __device__ __forceinline__ void resident_compute(const Mfma32Params& P, uint64_t
   const uint32_t sl = (uint32_t)(prod - gi.first);
   const uint8_t* slot = smem + sl * P.slot_bytes;
   v16i acc[2 * L - 1];
-  mfma32_tile<L>(P, slot, slot + L * P.a_plane, 32 * zt, 32 * ut, gi.v_lo, acc);
+  mfma32_tile<L, T4>(P, slot, slot + L * P.a_plane, 32 * zt, 32 * ut, gi.v_lo, acc);
   uint32_t li;
   const uint64_t gprod = global_product(P, prod, &li);
   mfma32_epilogue<L>(P, gprod, P.mods[li], P.rcent[li], 32 * zt, 32 * ut, acc);
@@ -668,7 +675,7 @@ __device__ __forceinline__ void resident_group(const Mfma32Params& P, uint64_t g
     stage_zero_fill<L>(P, gi, smem);
   }
   __syncthreads();
-  resident_compute<L>(P, grp, gi, smem);
+  resident_compute<L, !SMALL>(P, grp, gi, smem);  // SMALL: n < 4, t = n
 }
 
 // The K window of one run of a K-split group (one product, t >= 32, so the group's
