@@ -200,8 +200,8 @@ def test_plan_k_window_runs(t):
     to one K-step per run (share 10 %), two to four limbs; n = 128 on 128-wide tiles
     must not be split (its staging runs need n >= 256)."""
     rng = np.random.Generator(np.random.PCG64(41 + t))
-    specs = [(8192, 1068236801, 2), (4096, 3329, 2), (2048, (1 << 24) - 3, 3), (1024, 1068236801, 3),
-             (256, 12289, 5), (128, 17, 3)]
+    specs = [(8192, 1068236801, 2), (8192, (1 << 24) - 3, 1), (4096, 3329, 2), (2048, (1 << 24) - 3, 3),
+             (1024, 1068236801, 3), (256, 12289, 5), (128, 17, 3)]
     groups, want = [], []
     for n, q, count in specs:
         a = rng.integers(0, q, size=(count, n), dtype=np.uint64).astype(np.uint32)
