@@ -232,3 +232,42 @@ def test_plan_k_window_runs(t):
     finally:
         for n, L in tiles:
             pm.polymul_tune_set(n, L, 0)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_plan_random_compositions(seed):
+    """Seeded random plans: 3-6 groups of random degree (4 .. 16384), modulus (2 .. 64
+    bits) and count, built at a random split share (K-split runs, windowed runs and
+    streamed blocks mixed), two replays each checked word for word against the oracle."""
+    rng = np.random.Generator(np.random.PCG64(1000 + seed))
+    moduli32 = [17, 3329, 12289, 65537, 7681, (1 << 24) - 3, 1068236801, 536903681, (1 << 32) - 5]
+    moduli64 = [inputs.GOLDILOCKS, (1 << 64) - 59, (1 << 40) + 15]
+    groups, refs = [], []
+    for _ in range(int(rng.integers(3, 7))):
+        n = int(2 ** rng.integers(2, 15))
+        wide = rng.random() < 0.2
+        pool = moduli64 if wide else moduli32
+        q = pool[int(rng.integers(len(pool)))]  # by index: a choice over the list would round 2^64 - 59 to float
+        count = int(rng.integers(1, max(2, min(40, (1 << 16) // n))))
+        dt = np.uint64 if wide else np.uint32
+        a = rng.integers(0, q, size=(count, n), dtype=np.uint64).astype(dt)
+        b = rng.integers(0, q, size=(count, n), dtype=np.uint64).astype(dt)
+        da, db = to_dev(a), to_dev(b)
+        groups.append((da, db, torch.zeros_like(da), n, q))
+        refs.append((oracle.negacyclic(a, b, q), dt))
+    share = int(rng.choice([10, 30, 70, 140, 400]))
+    pm.polymul_tune_param_set("plan_share_pct", share)
+    try:
+        plan = pm.Plan(groups)
+    finally:
+        pm.polymul_tune_param_set("plan_share_pct", 140)
+    for rep in range(2):
+        for g in groups:
+            g[2].zero_()
+        plan.execute()
+        torch.cuda.synchronize()
+        for (da, db, dc, n, q), (wv, dt) in zip(groups, refs):
+            got = to_host(dc, dt)
+            assert np.array_equal(got, wv), f"seed {seed}, share {share}, replay {rep}, n={n}, q={q}: " + \
+                mismatch_report(got, wv)
+    plan.close()
