@@ -99,17 +99,35 @@ def _check(status, where):
 
 
 def _stream(stream):
+    """The HIP stream to launch on: `stream`, else torch's current stream on the current
+    device (read as a raw handle: building a torch Stream object costs ~3 us a call)."""
     import torch
     if stream is None:
+        raw = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+        if raw is not None:
+            dev = getattr(torch._C, "_cuda_getDevice", torch.cuda.current_device)
+            return ctypes.c_void_p(raw(dev()))
         stream = torch.cuda.current_stream()
     return ctypes.c_void_p(stream.cuda_stream)
+
+
+_INT_WORDS = {}  # bytes per word -> the integer dtypes of that width
+
+
+def _int_dtypes(nbytes):
+    if nbytes not in _INT_WORDS:
+        import torch
+        cands = [getattr(torch, n, None) for n in ("int8", "uint8", "int16", "uint16", "int32", "uint32",
+                                                   "int64", "uint64")]
+        _INT_WORDS[nbytes] = frozenset(d for d in cands if d is not None and d.itemsize == nbytes)
+    return _INT_WORDS[nbytes]
 
 
 def _words(t, nbytes, name):
     import torch
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise TypeError(f"{name} must be a device tensor")
-    if t.element_size() != nbytes or t.is_floating_point() or t.is_complex():
+    if t.dtype not in _int_dtypes(nbytes):
         raise TypeError(f"{name} must hold {8 * nbytes}-bit integer words")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
@@ -127,7 +145,7 @@ def _result(out, like, nbytes, name="out"):
         raise TypeError(f"{name} must be a tensor")
     if tuple(out.shape) != tuple(like.shape):
         raise ValueError(f"{name} has shape {tuple(out.shape)}, the result needs {tuple(like.shape)}")
-    if out.element_size() != nbytes or out.is_floating_point() or out.is_complex():
+    if out.dtype not in _int_dtypes(nbytes):
         raise ValueError(f"{name} must hold {8 * nbytes}-bit integer words")
     return out
 
