@@ -343,13 +343,16 @@ __device__ __forceinline__ void stream_block(const StreamParams& P, uint64_t ite
     }
     // ---- this chunk's MFMAs
     if (active) {
-      const uint8_t* abuf = smem + (c & 1) * (L * P.a_win);
+      // the lane's dword base and byte shift are fixed: a K-step moves the runs by a
+      // multiple of four bytes (for t = 1 or 2, n = t and d is always 0)
+      const uint8_t* abuf = smem + (c & 1) * (L * P.a_win) + 4 * (S_base >> 2);
+      const uint32_t sh = (uint32_t)(S_base & 3);
       const int D0 = c * (int)P.dc;
       uint32_t araw[L][5];
       v4i af[L], b[L];
       auto S_of = [&](int st) {
         const int dl = st >> P.log2spd;
-        return S_base + ((int)P.dc - 1 - dl) * t + ((st & ((int)P.spd - 1)) << 5);
+        return ((int)P.dc - 1 - dl) * t + ((st & ((int)P.spd - 1)) << 5);
       };
       auto B_of = [&](int st) {
         const int d = D0 + (st >> P.log2spd);
@@ -357,14 +360,13 @@ __device__ __forceinline__ void stream_block(const StreamParams& P, uint64_t ite
       };
       // af: step st aligned; araw: step st + 1's runs; the last steps re-read their own
       araw_load<L>(araw, abuf, P.a_win, S_of(0));
-      a_align<L>(af, araw, (uint32_t)(S_of(0) & 3));
+      a_align<L>(af, araw, sh);
       araw_load<L>(araw, abuf, P.a_win, S_of(steps > 1 ? 1 : 0));
       b_load<L>(b, ring, kRing * P.rs, B_of(0));
       for (int st = 0; st < steps; ++st) {
         const int sn = st + 1 < steps ? st + 1 : st;
         const int s2 = st + 2 < steps ? st + 2 : steps - 1;
-        mfma_step_tail<L>(acc, af, araw, (uint32_t)(S_of(sn) & 3), abuf, P.a_win, S_of(s2), b, ring,
-                          kRing * P.rs, B_of(sn));
+        mfma_step_tail<L>(acc, af, araw, sh, abuf, P.a_win, S_of(s2), b, ring, kRing * P.rs, B_of(sn));
       }
       if (!more || (c + 1 - c0) % (int)P.flush_every == 0) stream_flush<L, W>(acc, res, m);
     }
@@ -468,8 +470,8 @@ __device__ __forceinline__ void load_run(uint32_t (&x)[5], const uint8_t* plane,
 template <int PAR>
 __device__ __forceinline__ void mfma_step_par(v16i (&acc)[8], v4i& a, uint32_t (&x)[2][5], v4i (&b)[8],
                                               const uint8_t* abuf, uint32_t a_win, int S, int S_next,
-                                              const uint8_t* ring, uint32_t b_plane, int boff_next) {
-  const uint32_t sh = (uint32_t)(S & 3), sh_next = (uint32_t)(S_next & 3);
+                                              const uint8_t* ring, uint32_t b_plane, int boff_next, uint32_t sh) {
+  const uint32_t sh_next = sh;
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
 #pragma unroll
@@ -489,13 +491,18 @@ __device__ __forceinline__ void mfma_step_par(v16i (&acc)[8], v4i& a, uint32_t (
   }
 }
 
-// The K loop of one chunk for this wave's parity.
+// The K loop of one chunk for this wave's parity.  A K-step moves the A runs by
+// (dc - 1 - d) t + 32 c bytes, a multiple of four: for t = 1 or 2 (n = t, r = 1) d is
+// always 0.  So each run keeps the byte shift S_base & 3 and the lane's dword base,
+// and a step adds a uniform offset.
 template <int PAR>
 __device__ __forceinline__ void chunk_mfma_par(v16i (&acc)[8], const uint8_t* abuf, uint32_t a_win,
                                                const uint8_t* ring, uint32_t b_plane, int S_base, int dc, int t,
                                                int spd, uint32_t log2spd, int D0, int u0, int zl, int g, int rs,
                                                int steps) {
-  auto S_of = [&](int st) { return S_base + (dc - 1 - (st >> log2spd)) * t + ((st & (spd - 1)) << 5); };
+  abuf += 4 * (S_base >> 2);
+  const uint32_t sh = (uint32_t)(S_base & 3);
+  auto S_of = [&](int st) { return (dc - 1 - (st >> log2spd)) * t + ((st & (spd - 1)) << 5); };
   auto B_of = [&](int st) {
     const int d = D0 + (st >> log2spd);
     return ((u0 + zl - d) & (kRing - 1)) * rs + ((st & (spd - 1)) << 5) + 16 * g;
@@ -507,12 +514,12 @@ __device__ __forceinline__ void chunk_mfma_par(v16i (&acc)[8], const uint8_t* ab
   uint32_t x[2][5];
   const int S0 = S_of(0);
   load_run(x[0], abuf, S0);
-  v4i a = align_run(x[0], (uint32_t)(S0 & 3));
+  v4i a = align_run(x[0], sh);
   load_run(x[0], abuf + a_win, S0);
   load_run(x[1], abuf + 2 * a_win, S0);
   for (int st = 0; st < steps; ++st) {
     const int sn = st + 1 < steps ? st + 1 : st;  // the last step re-reads its own runs
-    mfma_step_par<PAR>(acc, a, x, b, abuf, a_win, S_of(st), S_of(sn), ring, b_plane, B_of(sn));
+    mfma_step_par<PAR>(acc, a, x, b, abuf, a_win, S_of(st), S_of(sn), ring, b_plane, B_of(sn), sh);
   }
 }
 
