@@ -133,23 +133,41 @@ __device__ __forceinline__ void crt_stage_pass(const Mfma32Params& P, const CrtC
       flags[k] = (rp >= 0 && rp < (int)P.b_rows ? 1u : 0u) | (rn >= 0 && rn < (int)P.b_rows ? 2u : 0u);
     }
   }
+  auto store = [&](int c, int k, uint32_t d) {
+    uint8_t* plane = smem + c * pstride[k];
+    if (flags[k] & 1u) *(uint32_t*)(plane + dst1[k]) = d;
+    if (flags[k] & 2u) *(uint32_t*)(plane + dst2[k]) = neg_bytes(d);
+  };
 #pragma unroll 1
   for (int c = 0; c < CP; ++c) {
     const uint32_t m = K.m[c0 + c];
+    if (m == 256) {  // uniform: the centred residue is the low byte
+#pragma unroll
+      for (int k = 0; k < kStageItems; ++k) {
+        if (!flags[k]) continue;
+        const uint32_t lo01 = __builtin_amdgcn_perm((uint32_t)v[k][1], (uint32_t)v[k][0], 0x0c0c0400u);
+        const uint32_t lo23 = __builtin_amdgcn_perm((uint32_t)v[k][3], (uint32_t)v[k][2], 0x0c0c0400u);
+        store(c, k, __builtin_amdgcn_perm(lo23, lo01, 0x05040100u));
+      }
+      continue;
+    }
     const int32_t r16 = K.r16[c0 + c];
     const float mf = K.mf[c0 + c], im = K.invm[c0 + c];
+    // v = 2^16 vh + vl, x = vh (2^16 mod m) + vl, r = x - m rint(x / m) as in
+    // residue_centred; |r| <= m/2 + 1 leaves r > 127 only for m = 254, 255 (folded to
+    // r - m), so the fold needs no test of m
+    auto res = [&](int32_t vv) {
+      const int32_t x = __mul24(vv >> 16, r16) + (vv & 0xFFFF);
+      const float xf = (float)x;
+      const int32_t r = (int32_t)fmaf(-rintf(xf * im), mf, xf);
+      return (uint32_t)(r > 127 ? r - (int32_t)m : r);
+    };
 #pragma unroll
     for (int k = 0; k < kStageItems; ++k) {
       if (!flags[k]) continue;
-      const uint32_t r0 = (uint32_t)residue_centred(v[k][0], m, r16, mf, im);
-      const uint32_t r1 = (uint32_t)residue_centred(v[k][1], m, r16, mf, im);
-      const uint32_t r2 = (uint32_t)residue_centred(v[k][2], m, r16, mf, im);
-      const uint32_t r3 = (uint32_t)residue_centred(v[k][3], m, r16, mf, im);
-      const uint32_t d = __builtin_amdgcn_perm(__builtin_amdgcn_perm(r3, r2, 0x0c0c0400u),
-                                               __builtin_amdgcn_perm(r1, r0, 0x0c0c0400u), 0x05040100u);
-      uint8_t* plane = smem + c * pstride[k];
-      if (flags[k] & 1u) *(uint32_t*)(plane + dst1[k]) = d;
-      if (flags[k] & 2u) *(uint32_t*)(plane + dst2[k]) = neg_bytes(d);
+      const uint32_t r0 = res(v[k][0]), r1 = res(v[k][1]), r2 = res(v[k][2]), r3 = res(v[k][3]);
+      store(c, k, __builtin_amdgcn_perm(__builtin_amdgcn_perm(r3, r2, 0x0c0c0400u),
+                                        __builtin_amdgcn_perm(r1, r0, 0x0c0c0400u), 0x05040100u));
     }
   }
 }
