@@ -169,3 +169,24 @@ def test_workload3_groups_full():
     for g in w.groups:
         _check(pm.polymul_negacyclic, g.a, g.b, g.q)
 
+
+
+def test_launches_go_to_the_current_stream():
+    """With no stream given, a call launches on torch's current stream of the current
+    device (read as a raw handle), also when the caller has made another stream current."""
+    from paper_2307_06554_amd import binding
+    q = 1068236801
+    rng = np.random.Generator(np.random.PCG64(77))
+    a = rng.integers(0, q, size=(64, 1024), dtype=np.uint64).astype(np.uint32)
+    b = rng.integers(0, q, size=(64, 1024), dtype=np.uint64).astype(np.uint32)
+    da, db = to_dev(a), to_dev(b)
+    assert (binding._stream(None).value or 0) == torch.cuda.current_stream().cuda_stream
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        assert binding._stream(None).value == s.cuda_stream
+        dc = pm.polymul_negacyclic(da, db, q)
+    s.synchronize()
+    got = to_host(dc, np.uint32)
+    wv = oracle.negacyclic(a, b, q)
+    assert np.array_equal(got, wv), mismatch_report(got, wv)
