@@ -231,6 +231,9 @@ def main():
                     help="seconds of oracle work for cpu_baseline (and the parity check of the timed output)")
     ap.add_argument("--preheat-s", type=float, default=1.0,
                     help="untimed seconds of the headline launch before its warm-up steps (clock settling)")
+    ap.add_argument("--preheat-route", choices=("direct", "crt", "karatsuba", "plain"), default="direct",
+                    help="the route the untimed preheat runs on the headline batch (direct: the timed "
+                         "launch itself; the others hold the GPU on that route, e.g. to read its power draw)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--all", action="store_true", help="also time the other workloads (stderr)")
     ap.add_argument("--karatsuba-depth", type=int, default=0,
@@ -267,7 +270,21 @@ def main():
     c = torch.empty_like(a)
 
     headline = lambda: pm.polymul_negacyclic_rns(a, b, w.qs, out=c)
-    pre_launches, pre_s = preheat(headline, args.preheat_s)
+    pre_fn = headline
+    if args.preheat_route == "crt":
+        c_pre = torch.empty_like(a)
+        pre_fn = lambda: pm.polymul_negacyclic_rns_crt(a, b, w.qs, out=c_pre)
+    elif args.preheat_route == "karatsuba":
+        d_pre = pm.polymul_tune_get_karatsuba(n, products, 4) or 2
+        ws_pre = torch.empty(max(16, pm.polymul_karatsuba_workspace_size(n, L, B, d_pre)), dtype=torch.uint8,
+                             device=dev)
+        c_pre = torch.empty_like(a)
+        pre_fn = lambda: pm.polymul_negacyclic_rns_karatsuba(a, b, w.qs, d_pre, workspace=ws_pre, out=c_pre)
+    elif args.preheat_route == "plain":
+        a0, b0, c_pre = a[:, 0].contiguous(), b[:, 0].contiguous(), torch.empty((B, n), dtype=torch.int32,
+                                                                                device=dev)
+        pre_fn = lambda: pm.polymul_negacyclic_plain(a0, b0, w.qs[0], out=c_pre)
+    pre_launches, pre_s = preheat(pre_fn, args.preheat_s)
     ms = time_steps(headline, args.steps, args.warmup)
     value = products / (ms / 1e3)
     c_timed = c.cpu().numpy().view(np.uint32).copy()  # output of the timed launches
@@ -339,7 +356,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "preheat": {"launches": pre_launches, "seconds": round(pre_s, 3)},
+        "preheat": {"launches": pre_launches, "seconds": round(pre_s, 3), "route": args.preheat_route},
         "ms_per_step": ms,
         "higher_is_better": True,
         "scaling": "weak",
