@@ -66,3 +66,9 @@ def test_profile_figures_only_for_the_sources_they_were_taken_on(monkeypatch):
     monkeypatch.setattr(tune, "csrc_hash", lambda: "0000000000000000")
     assert bench.measured_traffic() is None
     assert bench.measured_mfma_busy() is None
+
+
+def test_preheat_route_choices():
+    res = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--preheat-route", "ntt"],
+                         capture_output=True, text=True, timeout=120)
+    assert res.returncode == 2 and "invalid choice" in res.stderr
