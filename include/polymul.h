@@ -148,7 +148,11 @@ polymul_status polymul_plan_destroy(polymul_plan* plan);
  *
  * Arguments, layout and errors as polymul_negacyclic / polymul_negacyclic_rns;
  * n <= 4096 (the residue planes of both operands live in LDS), else
- * POLYMUL_EUNSUPPORTED.
+ * POLYMUL_EUNSUPPORTED.  Speed: at n = 4096 (one product's four output tiles share
+ * their operand fragments in 2 x 2) this route runs 1.1x the limb route; below, each
+ * product is a single output tile, every MFMA reads its own fragments and the
+ * channels' planes leave one workgroup per CU, and the limb route is much faster
+ * (n = 1024: about 7x, n = 512: about 14x).
  */
 polymul_status polymul_negacyclic_crt(const uint32_t* a, const uint32_t* b, uint32_t* c,
                                       uint64_t n, uint32_t q, uint64_t batch, hipStream_t stream);
